@@ -1,0 +1,266 @@
+"""Space-time multigrid: hierarchy, transfers, cell-wise additive Schwarz, V-cycle.
+
+Section 4 of the paper.  Readings where the paper is silent:
+  * hierarchy (Alg. mg-sequence, spatial levels only): halve p while p > min_p
+    (4 -> 2 -> 1, 3 -> 1, 2 -> 1), then halve the cell count per direction while
+    it stays even and >= 2 * coarse_cells; coarse h-levels use the even-index
+    vertex subset and re-discretise (coefficient lookup in spatial.Space).
+  * transfers (Section 4.2): prolongation evaluates the coarse Q_p function at
+    the fine nodes through the fine node's reference coordinates in its coarse
+    parent cell (the L2 embedding of nested spaces); restriction is the exact
+    transpose.  Both act on interior nodes only (Dirichlet rows/columns dropped).
+  * smoother (eqs. vanka0, vanka): blocks are the interior DoFs of one spatial
+    cell times the temporal DoFs of one time cell; the block matrix is the
+    principal submatrix of the assembled level operator, inverted densely; every
+    Dirichlet DoF is its own 1x1 identity block.  One step is
+    u <- u + omega * sum_T R_T^T S_TT^{-1} R_T (f - S u).
+  * omega (eq. relaxation): 2 / (lambda_max + lambda_min) from real parts of the
+    Ritz values of 15 Arnoldi steps on ASM * S, clamped to (0, 1].
+  * coarsest level: exact sparse LU.  V-cycle: Alg. stmg with nu1 = nu2 = n_smooth
+    and zero initial guesses.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import basis, spatial, spacetime, temporal
+
+
+# --------------------------------------------------------------------------- hierarchy
+
+def level_spaces(fine: spatial.Space, min_p: int = 1, coarse_cells: int = 2) -> List[spatial.Space]:
+    """Spaces from finest to coarsest."""
+    out = [fine]
+    cur = fine
+    while cur.p > min_p:
+        cur = spatial.Space(dim=cur.dim, cells=cur.cells, p=max(min_p, cur.p // 2), verts=cur.verts,
+                            lo=cur.lo, hi=cur.hi, coef_fine=cur.coef_fine,
+                            fine_cells=cur.fine_cells, ratio=cur.ratio)
+        out.append(cur)
+    while all(c % 2 == 0 and c // 2 >= coarse_cells for c in cur.cells):
+        verts = None
+        if cur.verts is not None:
+            sl = tuple(slice(None, None, 2) for _ in range(cur.dim)) + (slice(None),)
+            verts = np.ascontiguousarray(cur.verts[sl])
+        cur = spatial.Space(dim=cur.dim, cells=tuple(c // 2 for c in cur.cells), p=cur.p,
+                            verts=verts, lo=cur.lo, hi=cur.hi, coef_fine=cur.coef_fine,
+                            fine_cells=cur.fine_cells, ratio=cur.ratio * 2)
+        out.append(cur)
+    return out
+
+
+def _node_reference(space: spatial.Space):
+    """Per lattice node of `space`: a containing cell (coords) and the reference coordinate."""
+    nodes1 = basis.gauss_lobatto(space.n)
+    per_dim = []
+    for d in range(space.dim):
+        g = np.arange(space.nodes[d])
+        cell = np.minimum(g // space.p, space.cells[d] - 1)
+        loc = g - cell * space.p
+        per_dim.append((cell, nodes1[loc]))
+    return per_dim
+
+
+def prolongation(coarse: spatial.Space, fine: spatial.Space) -> sp.csr_matrix:
+    """P[g_f, g_c] = coarse basis function g_c evaluated at fine node g_f (all lattice nodes)."""
+    if coarse.cells == fine.cells:
+        h_ratio = 1
+    else:
+        h_ratio = fine.cells[0] // coarse.cells[0]
+    cnodes = basis.gauss_lobatto(coarse.n)
+    fref = _node_reference(fine)
+    rows_1d = []
+    for d in range(fine.dim):
+        fcell, fxi = fref[d]
+        ccell = np.minimum(fcell // h_ratio, coarse.cells[d] - 1)
+        cxi = ((fcell - ccell * h_ratio) + fxi) / h_ratio
+        V, _ = basis.lagrange(cnodes, cxi)                          # (N_f_d, p_c + 1)
+        rows_1d.append((ccell, V))
+    # d-dimensional evaluation: product of 1D factors over the coarse cell's nodes
+    Nf = fine.nodes
+    Nc = coarse.nodes
+    grids = np.meshgrid(*[np.arange(m) for m in Nf[::-1]], indexing="ij")
+    gf = [g.ravel() for g in grids[::-1]]
+    nloc = coarse.n
+    locs = np.meshgrid(*[np.arange(nloc)] * fine.dim, indexing="ij")
+    locs = [l.ravel() for l in locs[::-1]]
+    rows, cols, vals = [], [], []
+    fidx = np.zeros(len(gf[0]), dtype=np.int64)
+    stride = 1
+    for d in range(fine.dim):
+        fidx += gf[d] * stride
+        stride *= Nf[d]
+    for a in range(len(locs[0])):
+        val = np.ones(len(gf[0]))
+        cidx = np.zeros(len(gf[0]), dtype=np.int64)
+        stride = 1
+        for d in range(fine.dim):
+            ccell, V = rows_1d[d]
+            val = val * V[gf[d], locs[d][a]]
+            cidx += (ccell[gf[d]] * coarse.p + locs[d][a]) * stride
+            stride *= Nc[d]
+        nz = np.abs(val) > 0
+        rows.append(fidx[nz])
+        cols.append(cidx[nz])
+        vals.append(val[nz])
+    P = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(fine.n_x, coarse.n_x))
+    # a fine node on a coarse cell interface receives the same value from both sides;
+    # the construction above visits exactly one coarse cell per fine node.
+    return P
+
+
+# --------------------------------------------------------------------------- smoother
+
+@dataclass
+class Level:
+    op: spacetime.SlabOperator
+    S: sp.csr_matrix
+    blocks: list = field(default_factory=list)       # (index array, dense inverse)
+    omega: float = 1.0
+    P: Optional[sp.csr_matrix] = None                # from the next coarser level to this one
+    lu: object = None
+
+
+def asm_blocks(op: spacetime.SlabOperator, S: sp.csr_matrix):
+    """(indices, inverse of the principal submatrix) for every space-time cell K x I_m."""
+    space, sl = op.space, op.slab
+    dofs = space.cell_dofs()
+    bm = op.bmask
+    nc = sl.nt_cell
+    c = sl.n_t // nc
+    Nx = space.n_x
+    S = S.tocsr()
+    out = []
+    for K in range(space.n_cells):
+        sdofs = dofs[K][~bm[dofs[K]]]
+        if len(sdofs) == 0:
+            continue
+        for m in range(c):
+            idx = np.concatenate([(m * nc + i) * Nx + sdofs for i in range(nc)])
+            B = S[idx][:, idx].toarray()
+            out.append((idx, np.linalg.inv(B)))
+    return out
+
+
+def asm_apply(level: Level, r: np.ndarray) -> np.ndarray:
+    """sum_T R_T^T S_TT^{-1} R_T r, plus the identity on Dirichlet DoFs."""
+    r = r.ravel()
+    z = np.zeros_like(r)
+    for idx, inv in level.blocks:
+        z[idx] += inv @ r[idx]
+    nt = level.op.n_t
+    bfull = np.tile(level.op.bmask, nt)
+    z[bfull] += r[bfull]
+    return z
+
+
+def smooth(level: Level, f: np.ndarray, u: np.ndarray, steps: int, omega: Optional[float] = None):
+    w = level.omega if omega is None else omega
+    f = f.ravel()
+    u = u.ravel().copy()
+    for _ in range(steps):
+        u = u + w * asm_apply(level, f - level.S @ u)
+    return u
+
+
+def arnoldi_start(n_t: int, bmask: np.ndarray) -> np.ndarray:
+    """Deterministic start vector 1 + sin(0.7 g + 1.3 i + 0.1)/2 on interior DoFs."""
+    g = np.arange(len(bmask), dtype=np.float64)
+    i = np.arange(n_t, dtype=np.float64)
+    v = 1.0 + 0.5 * np.sin(0.7 * g[None, :] + 1.3 * i[:, None] + 0.1)
+    v[:, bmask] = 0.0
+    return v.ravel()
+
+
+def estimate_omega(level: Level, steps: int = 15) -> float:
+    """omega = 2/(lambda_max + lambda_min) from Arnoldi Ritz values of ASM * S."""
+    v = arnoldi_start(level.op.n_t, level.op.bmask)
+    n = len(v)
+    V = np.zeros((steps + 1, n))
+    H = np.zeros((steps + 1, steps))
+    V[0] = v / np.linalg.norm(v)
+    m = steps
+    for j in range(steps):
+        w = asm_apply(level, level.S @ V[j])
+        for i in range(j + 1):
+            H[i, j] = V[i] @ w
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] < 1e-14:
+            m = j + 1
+            break
+        V[j + 1] = w / H[j + 1, j]
+    ev = np.linalg.eigvals(H[:m, :m]).real
+    om = 2.0 / (ev.max() + ev.min())
+    return float(min(max(om, 1e-3), 1.0))
+
+
+# --------------------------------------------------------------------------- hierarchy object
+
+class Hierarchy:
+    """Levels ordered coarsest (index 0) to finest (index L), as in Alg. stmg."""
+
+    def __init__(self, fine_op: spacetime.SlabOperator, min_p: int = 1, coarse_cells: int = 2,
+                 omegas: Optional[List[float]] = None, n_smooth: int = 1):
+        spaces = level_spaces(fine_op.space, min_p, coarse_cells)[::-1]
+        self.n_smooth = n_smooth
+        self.levels: List[Level] = []
+        for i, space in enumerate(spaces):
+            op = fine_op if i == len(spaces) - 1 else spacetime.build(space, fine_op.slab)
+            lev = Level(op=op, S=op.matrix())
+            if i == 0:
+                lev.lu = spla.splu(lev.S.tocsc())
+            else:
+                lev.blocks = asm_blocks(op, lev.S)
+                lev.P = prolongation(spaces[i - 1], space)
+            self.levels.append(lev)
+        for i, lev in enumerate(self.levels):
+            if i == 0:
+                continue
+            if omegas is not None:
+                lev.omega = omegas[i]
+            else:
+                lev.omega = estimate_omega(lev)
+
+    @property
+    def omegas(self):
+        return [lev.omega for lev in self.levels]
+
+    def prolong(self, i: int, ec: np.ndarray) -> np.ndarray:
+        """Level i-1 -> level i on interior nodes, applied to every temporal row."""
+        lev, coarse = self.levels[i], self.levels[i - 1]
+        E = ec.reshape(coarse.op.n_t, coarse.op.n_x) * (~coarse.op.bmask)[None, :]
+        out = (lev.P @ E.T).T
+        out[:, lev.op.bmask] = 0.0
+        return out.ravel()
+
+    def restrict(self, i: int, r: np.ndarray) -> np.ndarray:
+        """Level i -> level i-1: the transpose of prolong."""
+        lev, coarse = self.levels[i], self.levels[i - 1]
+        R = r.reshape(lev.op.n_t, lev.op.n_x) * (~lev.op.bmask)[None, :]
+        out = (lev.P.T @ R.T).T
+        out[:, coarse.op.bmask] = 0.0
+        return out.ravel()
+
+    def vcycle(self, f: np.ndarray, i: Optional[int] = None) -> np.ndarray:
+        """Alg. stmg with zero initial guess: returns u ~ S_i^{-1} f."""
+        if i is None:
+            i = len(self.levels) - 1
+        lev = self.levels[i]
+        f = f.ravel()
+        if i == 0:
+            return lev.lu.solve(f)
+        u = np.zeros_like(f)
+        u = smooth(lev, f, u, self.n_smooth)
+        r = f - lev.S @ u
+        ec = self.vcycle(self.restrict(i, r), i - 1)
+        u = u + self.prolong(i, ec)
+        u = smooth(lev, f, u, self.n_smooth)
+        return u

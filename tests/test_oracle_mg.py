@@ -1,0 +1,122 @@
+"""Pins of the oracle's multigrid parts (Section 4: transfers, ASM smoother, V-cycle)."""
+import numpy as np
+import pytest
+
+from oracle import krylov, mg, spacetime, spatial, temporal
+from stmg_inputs import Config, draw_problem, random_slab_vector, small_configs
+
+
+def _op(cfg):
+    verts, coef = draw_problem(cfg)
+    return spacetime.from_config(cfg, verts, coef)
+
+
+@pytest.mark.parametrize("dim,pc,pf,hc,hf", [(2, 1, 2, 3, 3), (3, 2, 4, 2, 2), (2, 2, 2, 2, 4),
+                                             (3, 1, 1, 2, 4), (3, 1, 3, 2, 2)])
+def test_prolongation_reproduces_coarse_polynomials(dim, pc, pf, hc, hf):
+    # nested spaces: interpolating a Q_pc polynomial on the coarse lattice and prolongating
+    # gives the fine-lattice interpolant of the same polynomial
+    cells_c, cells_f = (hc,) * dim, (hf,) * dim
+    one = np.ones(int(np.prod(cells_f)))
+    fine = spatial.Space(dim, cells_f, pf, None, (0,) * dim, (1,) * dim, one, cells_f, 1)
+    coarse = spatial.Space(dim, cells_c, pc, None, (0,) * dim, (1,) * dim, one, cells_f, hf // hc)
+    P = mg.prolongation(coarse, fine)
+    rng = np.random.default_rng(1)
+    coeff = rng.standard_normal((pc + 1,) * dim)
+
+    def poly(X):
+        val = np.zeros(len(X))
+        for idx in np.ndindex(*coeff.shape):
+            term = coeff[idx] * np.ones(len(X))
+            for d in range(dim):
+                term = term * X[:, d] ** idx[d]
+            val += term
+        return val
+
+    uc = poly(spatial.node_coordinates(coarse))
+    uf = poly(spatial.node_coordinates(fine))
+    assert np.allclose(P @ uc, uf, atol=1e-12)
+    # partition of unity
+    assert np.allclose(P @ np.ones(coarse.n_x), 1.0, atol=1e-13)
+
+
+def test_restriction_is_adjoint():
+    cfg = small_configs()[1]
+    op = _op(cfg)
+    H = mg.Hierarchy(op, omegas=[1.0] * 3)
+    rng = np.random.default_rng(2)
+    for i in range(1, len(H.levels)):
+        nf = H.levels[i].S.shape[0]
+        nc = H.levels[i - 1].S.shape[0]
+        x = rng.standard_normal(nc)
+        y = rng.standard_normal(nf)
+        assert abs(H.prolong(i, x) @ y - x @ H.restrict(i, y)) < 1e-11 * np.sqrt(nf)
+
+
+@pytest.mark.parametrize("method,problem", [(0, 0), (1, 1)])
+def test_asm_single_cell_is_exact(method, problem):
+    # one spatial cell and one time cell: the ASM block is the whole interior system
+    cfg = Config(dim=3, problem=problem, time_method=method, p=3, k=2, n_time_cells=1,
+                 n_cells=(1, 1, 1), tau=0.2, perturb=0.0)
+    op = _op(cfg)
+    lev = mg.Level(op=op, S=op.matrix())
+    lev.blocks = mg.asm_blocks(op, lev.S)
+    b = random_slab_vector(cfg, 3)
+    u = mg.smooth(lev, b, np.zeros_like(b), 1, omega=1.0)
+    assert np.allclose(u, op.solve(b).ravel(), atol=1e-12)
+
+
+def test_asm_block_sizes():
+    # block size (k+1)(p+1)^d for dG(k) and k(p+1)^d for cGP(k) on interior cells (Section 4.3)
+    for method, k, per in [(0, 2, 3), (1, 2, 2)]:
+        cfg = Config(dim=3, time_method=method, k=k, p=2, n_time_cells=2, n_cells=(3, 3, 3), tau=0.1)
+        op = _op(cfg)
+        blocks = mg.asm_blocks(op, op.matrix())
+        assert max(len(idx) for idx, _ in blocks) == per * 27
+        assert len(blocks) == 27 * 2
+
+
+def test_asm_blocks_are_principal_submatrices():
+    cfg = Config(dim=2, time_method=1, problem=1, k=2, p=2, n_time_cells=3, n_cells=(3, 3, 1),
+                 tau=0.1, perturb=0.1, coef="lognormal", coef_sigma=1.0, seed=2)
+    op = _op(cfg)
+    S = op.matrix().toarray()
+    blocks = mg.asm_blocks(op, op.matrix())
+    for idx, inv in blocks[::5]:
+        assert np.allclose(inv @ S[np.ix_(idx, idx)], np.eye(len(idx)), atol=1e-10)
+        # the same spatial cell gives the same block in every time cell (M_tau, N~ repeat)
+    Nx = op.n_x
+    b0 = [b for b in blocks if b[0][0] // Nx < 2]
+    b2 = [b for b in blocks if b[0][0] // Nx >= 4]
+    assert np.allclose(b0[0][1], b2[0][1], atol=1e-12)
+
+
+@pytest.mark.parametrize("ci", [0, 1, 2])
+def test_vcycle_fgmres_reaches_direct_solution(ci):
+    cfg = small_configs()[ci]
+    op = _op(cfg)
+    H = mg.Hierarchy(op, n_smooth=1)
+    assert all(0 < w <= 1 for w in H.omegas)
+    b = random_slab_vector(cfg, 5)
+    x, it, rr = krylov.fgmres(op.apply, b, H.vcycle, rtol=1e-11, restart=40, max_iter=200)
+    xd = op.solve(b)
+    assert rr <= 1e-11
+    assert np.linalg.norm(x - xd.ravel()) <= 1e-9 * np.linalg.norm(xd)
+    assert it < 60
+
+
+def test_vcycle_is_linear_and_reduces_error():
+    cfg = small_configs()[1]
+    op = _op(cfg)
+    H = mg.Hierarchy(op, n_smooth=2)
+    b1 = random_slab_vector(cfg, 1)
+    b2 = random_slab_vector(cfg, 2)
+    z = H.vcycle(2.0 * b1 - 3.0 * b2)
+    assert np.allclose(z, 2.0 * H.vcycle(b1) - 3.0 * H.vcycle(b2), atol=1e-10)
+    # as a stationary iteration x <- x + V(b - S x) the error contracts
+    xd = op.solve(b1).ravel()
+    x = np.zeros_like(xd)
+    e0 = np.linalg.norm(xd)
+    for _ in range(6):
+        x = x + H.vcycle(b1.ravel() - op.apply(x))
+    assert np.linalg.norm(x - xd) < 0.5 * e0
