@@ -1,0 +1,183 @@
+/*
+ * stmg.h - C ABI of the MI355X space-time multigrid library (libstmg.so).
+ *
+ * The library solves one all-at-once time-slab system S u = b of a space-time
+ * finite element discretisation of the heat equation or of the acoustic wave
+ * equation (Margenberg & Munch, "A Space-Time Multigrid Method for Space-Time
+ * Finite Element Discretizations of Parabolic and Hyperbolic PDEs"):
+ *   - spatial continuous Q_p on a structured hexahedral (d = 3) or
+ *     quadrilateral (d = 2) mesh of [lo, hi], Cartesian or with displaced
+ *     vertices (multilinear cells), homogeneous Dirichlet data on the boundary
+ *     (Section 2, eqs. fespace and space-matrices);
+ *   - dG(k) or cGP(k) in time, c time cells batched into one slab
+ *     (Sections 3.1-3.2, eqs. heat-cg-dg-at-once, wave-cg-dg-at-once,
+ *     heat-cg-cg-at-once, wave-cg-cg-at-once).  For every pair the slab matrix
+ *     is S = M_T (x) A_h + N_T (x) M_h with small dense temporal factors M_T, N_T
+ *     (N_T = A_T for heat, A_T M_T^{-1} A_T for the condensed wave system);
+ *   - solver: flexible GMRES in FP64, preconditioned by one space-time multigrid
+ *     V-cycle per iteration (Section 4, Alg. stmg) with the space-time cell-wise
+ *     additive Schwarz smoother (eqs. vanka0 and vanka) and spatial h/p transfers
+ *     (Section 4.2, Alg. mg-sequence, spatial levels only).
+ *
+ * Vector layout (every device vector argument): time-major [n_t][N_x], where
+ * N_x = prod_d (p * n_cells[d] + 1) lattice nodes ordered x fastest, n_t =
+ * c (k+1) for dG(k) and c k for cGP(k).  Dirichlet (boundary) nodes are part of
+ * the vector; S acts as the identity on them.  Level 0 is the finest level.
+ *
+ * Ownership: all vector arguments are device pointers owned by the caller,
+ * contiguous, of the stated dtype, on the device that was current at
+ * stmg_create.  Host arrays passed to stmg_create are copied.  The library owns
+ * its workspace (allocated in stmg_create, released in stmg_destroy).
+ *
+ * Streams: every call enqueues its kernels on the hipStream_t given at
+ * creation.  stmg_vmult, stmg_smooth, stmg_vcycle, stmg_prolongate and
+ * stmg_restrict are asynchronous.  stmg_create and stmg_solve synchronise.
+ *
+ * Errors: every function returns an stmg_status; nothing is thrown or aborted
+ * across the ABI.  stmg_last_error() returns a thread-local message for the
+ * last failing call on the calling thread.  A handle must not be used by two
+ * host threads at the same time.
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STMG_ABI_VERSION 1
+
+typedef enum {
+  STMG_OK = 0,
+  STMG_E_ARG = 1,          /* invalid argument (null pointer, bad level/dtype, bad config) */
+  STMG_E_NOMEM = 2,        /* device or host allocation failed */
+  STMG_E_HIP = 3,          /* a HIP runtime or ROCm library call failed */
+  STMG_E_NOCONV = 4,       /* stmg_solve reached max_iter; info is still filled */
+  STMG_E_NONFINITE = 5,    /* NaN/Inf in the right-hand side or in the iteration */
+  STMG_E_UNSUPPORTED = 6,  /* configuration outside what the library implements */
+  STMG_E_STATE = 7         /* call not valid for this handle's state (e.g. no CNN weights) */
+} stmg_status;
+
+typedef enum { STMG_HEAT = 0, STMG_WAVE = 1 } stmg_problem;
+typedef enum { STMG_DG = 0, STMG_CGP = 1 } stmg_time_method;
+typedef enum { STMG_F64 = 0, STMG_F32 = 1 } stmg_dtype;
+typedef enum { STMG_PREC_FP64 = 0, STMG_PREC_FP32 = 1, STMG_PREC_LEARNED = 2 } stmg_precision;
+
+/* One slab problem and its solver settings.  Fields follow the paper's notation. */
+typedef struct {
+  int32_t abi_version;     /* must be STMG_ABI_VERSION */
+  int32_t dim;             /* 2 or 3 */
+  int32_t problem;         /* stmg_problem */
+  int32_t time_method;     /* stmg_time_method */
+  int32_t p;               /* spatial degree, 1..4 */
+  int32_t k;               /* temporal degree: dG 0..5, cGP 1..5 */
+  int32_t n_time_cells;    /* c >= 1, time cells in the slab */
+  int32_t n_cells[3];      /* cells per direction (n_cells[2] ignored for dim 2) */
+  double t0, tau;          /* slab start, time-cell length (> 0) */
+  double lo[3], hi[3];     /* Cartesian box (only used when vertices == NULL) */
+  int32_t n_smooth;        /* nu1 = nu2 smoothing steps per level, >= 1 */
+  int32_t min_p;           /* p-coarsening stops at this degree (>= 1) */
+  int32_t coarse_cells;    /* h-coarsening stops before a level has fewer cells per direction */
+  int32_t vcycle_dtypes;   /* bit 0: build FP64 V-cycle data, bit 1: FP32; 0 = from precision */
+  double omega;            /* > 0: relaxation used on every level; <= 0: estimate per level (eq. relaxation) */
+  int32_t precision;       /* stmg_precision: preconditioner used by stmg_solve */
+  int32_t restart;         /* FGMRES restart length m >= 1 */
+  int32_t max_iter;        /* total FGMRES iterations allowed */
+  int32_t reserved0;
+  double rtol;             /* stop at ||b - S x||_2 / ||b||_2 <= rtol (true residual) */
+  uint64_t seed;           /* reserved for randomised setup steps */
+} stmg_config;
+
+typedef struct {
+  int32_t iterations;      /* FGMRES iterations (one V-cycle each) */
+  int32_t restarts;
+  double rel_residual;     /* true relative residual ||b - S x|| / ||b|| at exit, FP64 */
+  double seconds;          /* wall time of the solve (host clock, after a device sync) */
+  double t_smoother;       /* event-timed buckets: ASM smoother applications */
+  double t_gmg_other;      /* V-cycle work other than the smoother (operators, transfers, coarse solve) */
+  double t_operator;       /* outer FP64 operator applications */
+  double t_other;          /* everything else: orthogonalisation, updates, casts, CNN */
+  int32_t cnn_used;        /* learned stage accepted this many times */
+  int32_t cnn_fallbacks;   /* learned stage rejected (plain V-cycle used) */
+} stmg_solve_info;
+
+#define STMG_MAX_LEVELS 16
+typedef struct {
+  int32_t n_levels;
+  int32_t n_t;
+  int32_t nt_cell;                          /* temporal DoFs per time cell */
+  int32_t reserved0;
+  int64_t n_x[STMG_MAX_LEVELS];             /* lattice nodes per level */
+  int32_t p[STMG_MAX_LEVELS];
+  int32_t cells[STMG_MAX_LEVELS][3];
+  double omega[STMG_MAX_LEVELS];            /* relaxation per level (0 on the coarsest) */
+  int64_t coarse_unknowns;                  /* interior unknowns of the coarsest level */
+  int64_t device_bytes;                     /* library-owned device memory */
+  double setup_seconds;
+} stmg_info;
+
+typedef struct stmg_handle stmg_handle;
+
+/* Build the level hierarchy, smoother factors, relaxation parameters and the
+ * coarse-level inverse (Section 4; Alg. mg-sequence with spatial levels).
+ * vertices: host, nullable.  NULL means a Cartesian box [lo, hi]; otherwise
+ *   (n_cells+1)^dim vertex positions, x fastest, dim doubles each.  Cells must
+ *   not be inverted (STMG_E_ARG otherwise).
+ * coeff: host, one positive coefficient per finest cell (rho of eqs. heat and
+ *   wave), x fastest; NULL means 1 everywhere.
+ * hip_stream: a hipStream_t (NULL = default stream).
+ * out: receives the handle; unchanged on failure. Synchronous. */
+stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const double* coeff,
+                        void* hip_stream, stmg_handle** out);
+
+/* y = S_level x (eq. lin-sys on that level), identity on Dirichlet nodes.
+ * dtype 0: x, y double; dtype 1: float.  x and y must not alias. */
+stmg_status stmg_vmult(stmg_handle* h, int level, int dtype, const void* x, void* y);
+
+/* n_steps damped additive Schwarz steps (eq. vanka):
+ * x <- x + omega_level * sum_T R_T^T [R_T S R_T^T]^{-1} R_T (b - S x),
+ * blocks T = interior DoFs of one spatial cell x one time cell (eq. vanka0);
+ * each Dirichlet DoF is its own identity block.  Requires the level's factors
+ * for dtype (vcycle_dtypes); level must not be the coarsest. */
+stmg_status stmg_smooth(stmg_handle* h, int level, int dtype, const void* b, void* x, int n_steps);
+
+/* z = V(r): one V-cycle of Alg. stmg on the finest level with zero initial
+ * guess, nu1 = nu2 = n_smooth, exact coarsest-level solve.  r, z must not alias. */
+stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z);
+
+/* fine = P coarse: prolongation from level+1 to level (Section 4.2): the coarse
+ * Q_p function evaluated at the fine nodes; Dirichlet values of coarse are
+ * treated as zero and fine Dirichlet values are written as zero. */
+stmg_status stmg_prolongate(stmg_handle* h, int level, int dtype, const void* coarse, void* fine);
+
+/* coarse = P^T fine (Section 4.2, restriction = adjoint of prolongation) on
+ * interior nodes; coarse Dirichlet values are written as zero. */
+stmg_status stmg_restrict(stmg_handle* h, int level, int dtype, const void* fine, void* coarse);
+
+/* Solve S x = b with FP64 flexible GMRES(restart) right-preconditioned by one
+ * V-cycle per iteration (Section 5 solver set-up; precision selects an FP64,
+ * FP32 or learned+FP32 preconditioner).  b, x: device double vectors; x holds
+ * the initial guess on entry.  Dirichlet entries of b and x are set to zero
+ * (homogeneous data).  Returns STMG_E_NOCONV (with info filled) if rtol is
+ * not reached within max_iter, STMG_E_NONFINITE for NaN/Inf.  Synchronous.
+ * info may be NULL. */
+stmg_status stmg_solve(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
+
+/* Override the relaxation parameter of one level (omega > 0). */
+stmg_status stmg_set_omega(stmg_handle* h, int level, double omega);
+
+/* Sizes and parameters of the hierarchy. */
+stmg_status stmg_query(stmg_handle* h, stmg_info* info);
+
+/* Release all device memory of the handle; NULL is ignored. */
+void stmg_destroy(stmg_handle* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* stmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STMG_H */

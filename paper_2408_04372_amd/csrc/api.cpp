@@ -1,0 +1,256 @@
+// C ABI entry points of libstmg (declared in include/stmg.h).  Every entry
+// point validates its arguments, runs the C++ implementation and converts any
+// exception into an stmg_status plus a thread-local message.
+#include <chrono>
+#include <cmath>
+#include <string>
+
+#include "handle.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class F>
+stmg_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const stmg::Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return STMG_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return STMG_E_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return STMG_E_HIP;
+  }
+}
+
+void check_config(const stmg_config* c) {
+  using stmg::fail;
+  if (!c) fail(STMG_E_ARG, "cfg is NULL");
+  if (c->abi_version != STMG_ABI_VERSION) fail(STMG_E_ARG, "abi_version mismatch");
+  if (c->dim != 2 && c->dim != 3) fail(STMG_E_ARG, "dim must be 2 or 3");
+  if (c->problem != STMG_HEAT && c->problem != STMG_WAVE) fail(STMG_E_ARG, "problem must be heat (0) or wave (1)");
+  if (c->time_method != STMG_DG && c->time_method != STMG_CGP) fail(STMG_E_ARG, "time_method must be dG (0) or cGP (1)");
+  if (c->p < 1 || c->p > 4) fail(STMG_E_UNSUPPORTED, "p must be in 1..4");
+  if (c->time_method == STMG_DG && (c->k < 0 || c->k > 5)) fail(STMG_E_UNSUPPORTED, "dG degree k must be in 0..5");
+  if (c->time_method == STMG_CGP && (c->k < 1 || c->k > 5)) fail(STMG_E_UNSUPPORTED, "cGP degree k must be in 1..5");
+  if (c->n_time_cells < 1) fail(STMG_E_ARG, "n_time_cells must be >= 1");
+  for (int d = 0; d < c->dim; ++d)
+    if (c->n_cells[d] < 1) fail(STMG_E_ARG, "n_cells must be >= 1");
+  if (!(c->tau > 0.0) || !std::isfinite(c->tau)) fail(STMG_E_ARG, "tau must be positive");
+  for (int d = 0; d < c->dim; ++d)
+    if (!(c->hi[d] > c->lo[d])) fail(STMG_E_ARG, "hi must exceed lo");
+  if (c->n_smooth < 1) fail(STMG_E_ARG, "n_smooth must be >= 1");
+  if (c->min_p < 1) fail(STMG_E_ARG, "min_p must be >= 1");
+  if (c->coarse_cells < 1) fail(STMG_E_ARG, "coarse_cells must be >= 1");
+  if (c->precision < 0 || c->precision > 2) fail(STMG_E_ARG, "precision must be 0, 1 or 2");
+  if (c->restart < 1 || c->restart > 200) fail(STMG_E_ARG, "restart must be in 1..200");
+  if (c->max_iter < 1) fail(STMG_E_ARG, "max_iter must be >= 1");
+  if (!(c->rtol > 0.0)) fail(STMG_E_ARG, "rtol must be positive");
+  if (c->vcycle_dtypes < 0 || c->vcycle_dtypes > 3) fail(STMG_E_ARG, "vcycle_dtypes must be in 0..3");
+  long long nx = 1;
+  for (int d = 0; d < c->dim; ++d) nx *= (long long)c->p * c->n_cells[d] + 1;
+  int per = c->time_method == STMG_DG ? c->k + 1 : c->k;
+  long long nst = nx * per * c->n_time_cells;
+  if (nst >= (1LL << 31)) fail(STMG_E_UNSUPPORTED, "more than 2^31 space-time DoFs");
+}
+
+// every multilinear cell must have a positive Jacobian determinant at its corners
+void check_vertices(const stmg_config* c, const double* v) {
+  int d = c->dim;
+  int nx = c->n_cells[0], ny = c->n_cells[1], nz = d == 3 ? c->n_cells[2] : 1;
+  auto P = [&](int x, int y, int z, int k) {
+    return v[(((size_t)z * (ny + 1) + y) * (nx + 1) + x) * d + k];
+  };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        for (int corner = 0; corner < (1 << d); ++corner) {
+          int bx = corner & 1, by = (corner >> 1) & 1, bz = (corner >> 2) & 1;
+          int sx = bx ? -1 : 1, sy = by ? -1 : 1, sz = bz ? -1 : 1;
+          double e[3][3];
+          for (int k = 0; k < d; ++k) {
+            e[0][k] = sx * (P(x + 1 - bx, y + by, z + bz, k) - P(x + bx, y + by, z + bz, k));
+            e[1][k] = sy * (P(x + bx, y + 1 - by, z + bz, k) - P(x + bx, y + by, z + bz, k));
+            if (d == 3) e[2][k] = sz * (P(x + bx, y + by, z + 1 - bz, k) - P(x + bx, y + by, z + bz, k));
+          }
+          double det;
+          if (d == 2) det = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+          else
+            det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                  e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                  e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+          if (!(det > 0.0)) stmg::fail(STMG_E_ARG, "inverted or degenerate cell in the vertex lattice");
+        }
+}
+
+stmg::Level& level_of(stmg_handle* h, int level) {
+  if (!h) stmg::fail(STMG_E_ARG, "handle is NULL");
+  if (level < 0 || level >= (int)h->levels.size()) stmg::fail(STMG_E_ARG, "level out of range");
+  return *h->levels[level];
+}
+
+void check_dtype(stmg_handle* h, int dtype, bool need_vcycle_data, int level) {
+  if (dtype != STMG_F64 && dtype != STMG_F32) stmg::fail(STMG_E_ARG, "dtype must be 0 (f64) or 1 (f32)");
+  if (!need_vcycle_data) return;
+  stmg::Level& L = *h->levels[level];
+  if (dtype == STMG_F64 && !L.has64) stmg::fail(STMG_E_STATE, "FP64 V-cycle data not built (vcycle_dtypes)");
+  if (dtype == STMG_F32 && !L.has32) stmg::fail(STMG_E_STATE, "FP32 V-cycle data not built (vcycle_dtypes)");
+}
+
+}  // namespace
+
+stmg_handle::~stmg_handle() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  else (void)hipDeviceSynchronize();
+  stmg::cnn_free(cnn);
+}
+
+extern "C" {
+
+stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const double* coeff, void* hip_stream,
+                        stmg_handle** out) {
+  return guarded([&]() -> stmg_status {
+    if (!out) stmg::fail(STMG_E_ARG, "out is NULL");
+    check_config(cfg);
+    if (vertices) check_vertices(cfg, vertices);
+    auto t0 = std::chrono::steady_clock::now();
+    int64_t bytes0 = stmg::DevBuf::total_bytes();
+    std::unique_ptr<stmg_handle> h(new stmg_handle());
+    h->cfg = *cfg;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    STMG_HIP(hipGetDevice(&h->device));
+    int dt = cfg->vcycle_dtypes;
+    if (dt == 0) dt = cfg->precision == STMG_PREC_FP64 ? 1 : 2;
+    h->want64 = (dt & 1) != 0;
+    h->want32 = (dt & 2) != 0;
+    stmg::build_hierarchy(h.get(), vertices, coeff);
+    h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    h->bytes_at_create = stmg::DevBuf::total_bytes() - bytes0;
+    *out = h.release();
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_vmult(stmg_handle* h, int level, int dtype, const void* x, void* y) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, level);
+    check_dtype(h, dtype, false, level);
+    if (!x || !y) stmg::fail(STMG_E_ARG, "x or y is NULL");
+    if (x == y) stmg::fail(STMG_E_ARG, "x and y must not alias");
+    if (dtype == STMG_F64) stmg::vmult<double>(h, level, (const double*)x, (double*)y);
+    else stmg::vmult<float>(h, level, (const float*)x, (float*)y);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_smooth(stmg_handle* h, int level, int dtype, const void* b, void* x, int n_steps) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, level);
+    if (level == (int)h->levels.size() - 1) stmg::fail(STMG_E_ARG, "the coarsest level has no smoother");
+    check_dtype(h, dtype, true, level);
+    if (!b || !x) stmg::fail(STMG_E_ARG, "b or x is NULL");
+    if (n_steps < 0) stmg::fail(STMG_E_ARG, "n_steps must be >= 0");
+    if (dtype == STMG_F64) stmg::smooth<double>(h, level, (const double*)b, (double*)x, n_steps);
+    else stmg::smooth<float>(h, level, (const float*)b, (float*)x, n_steps);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    check_dtype(h, dtype, true, 0);
+    if (!r || !z) stmg::fail(STMG_E_ARG, "r or z is NULL");
+    if (r == z) stmg::fail(STMG_E_ARG, "r and z must not alias");
+    if (dtype == STMG_F64) stmg::vcycle<double>(h, 0, (const double*)r, (double*)z);
+    else stmg::vcycle<float>(h, 0, (const float*)r, (float*)z);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_prolongate(stmg_handle* h, int level, int dtype, const void* coarse, void* fine) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, level);
+    if (level + 1 >= (int)h->levels.size()) stmg::fail(STMG_E_ARG, "level has no coarser level");
+    check_dtype(h, dtype, true, level);
+    if (!coarse || !fine) stmg::fail(STMG_E_ARG, "NULL vector");
+    if (dtype == STMG_F64) stmg::prolongate<double>(h, level, (const double*)coarse, (double*)fine, false);
+    else stmg::prolongate<float>(h, level, (const float*)coarse, (float*)fine, false);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_restrict(stmg_handle* h, int level, int dtype, const void* fine, void* coarse) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, level);
+    if (level + 1 >= (int)h->levels.size()) stmg::fail(STMG_E_ARG, "level has no coarser level");
+    check_dtype(h, dtype, true, level);
+    if (!coarse || !fine) stmg::fail(STMG_E_ARG, "NULL vector");
+    if (dtype == STMG_F64) stmg::restrict_<double>(h, level, (const double*)fine, (double*)coarse);
+    else stmg::restrict_<float>(h, level, (const float*)fine, (float*)coarse);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_solve(stmg_handle* h, const double* b, double* x, stmg_solve_info* info) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!b || !x) stmg::fail(STMG_E_ARG, "b or x is NULL");
+    if ((const void*)b == (const void*)x) stmg::fail(STMG_E_ARG, "b and x must not alias");
+    check_dtype(h, h->cfg.precision == STMG_PREC_FP64 ? STMG_F64 : STMG_F32, true, 0);
+    stmg_status st = stmg::fgmres(h, b, x, info);
+    if (st == STMG_E_NOCONV) g_last_error = "FGMRES did not reach rtol within max_iter";
+    if (st == STMG_E_NONFINITE) g_last_error = "non-finite value in the iteration";
+    return st;
+  });
+}
+
+stmg_status stmg_set_omega(stmg_handle* h, int level, double omega) {
+  return guarded([&]() -> stmg_status {
+    stmg::Level& L = level_of(h, level);
+    if (!(omega > 0.0) || !std::isfinite(omega)) stmg::fail(STMG_E_ARG, "omega must be positive");
+    L.omega = omega;
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_query(stmg_handle* h, stmg_info* info) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!info) stmg::fail(STMG_E_ARG, "info is NULL");
+    *info = stmg_info{};
+    info->n_levels = (int)h->levels.size();
+    info->n_t = h->tm.n_t;
+    info->nt_cell = h->tm.nt_cell;
+    for (size_t l = 0; l < h->levels.size(); ++l) {
+      const stmg::Level& L = *h->levels[l];
+      info->n_x[l] = L.g.nx;
+      info->p[l] = L.p;
+      for (int d = 0; d < 3; ++d) info->cells[l][d] = L.cells[d];
+      info->omega[l] = L.omega;
+    }
+    info->coarse_unknowns = h->levels.back()->cm;
+    info->device_bytes = h->bytes_at_create;
+    info->setup_seconds = h->setup_seconds;
+    return STMG_OK;
+  });
+}
+
+void stmg_destroy(stmg_handle* h) {
+  try {
+    delete h;
+  } catch (...) {
+  }
+}
+
+const char* stmg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Space-time cell-wise additive Schwarz smoother (Section 4.3, eqs. vanka0, vanka).
+//
+// The block of space-time cell K x I_m is the principal submatrix of the level
+// operator on K's interior nodes and I_m's temporal DoFs.  Because the slab
+// operator is M_T (x) A_h + N_T (x) M_h, that block is
+//     B_K = M_tau (x) A_KK + N~ (x) M_KK,
+// the same for every time cell m (M_tau, N~: diagonal blocks of M_T, N_T), with
+// A_KK, M_KK the principal submatrices of the assembled spatial matrices.  The
+// paper only uses this structure to avoid assembling S; here it also factorises
+// the local solve: with the generalised eigenpairs A_KK Q = M_KK Q Lambda,
+// Q^T M_KK Q = I,
+//     B_K^{-1} = (I (x) Q) blockdiag_s (lambda_s M_tau + N~)^{-1} (I (x) Q^T),
+// so one application per spatial cell is two dense [n_s x n_s] x [n_s x n_t]
+// products (all time cells of the slab at once) and n_s tiny N_t x N_t solves,
+// instead of a dense (N_t n_s)^2 inverse per block.  Dirichlet nodes inside a
+// block are decoupled (identity rows in A_KK and M_KK) and masked on input and
+// output, so they never receive a correction from the block.
+//
+// Set-up kernels: probe vectors for extracting A_KK / M_KK from the matrix-free
+// operator (3^d colours of cells whose node sets are far enough apart), the
+// extraction itself, and the per-mode temporal inverses.
+#include "kernels.hpp"
+
+namespace stmg {
+
+namespace {
+
+__device__ inline void cell_coords(long long cell, const GeomDesc& g, int& cx, int& cy, int& cz) {
+  cx = (int)(cell % g.nc[0]);
+  cy = (int)((cell / g.nc[0]) % g.nc[1]);
+  cz = (int)(cell / ((long long)g.nc[0] * g.nc[1]));
+}
+
+// node index and interior flag of local node r = lx + n (ly + n lz) of a cell
+__device__ inline long long node_of(const GeomDesc& g, int cx, int cy, int cz, int r, bool& interior) {
+  int n = g.n, p = g.p;
+  int lx = r % n, ly = (r / n) % n, lz = (g.dim == 3) ? r / (n * n) : 0;
+  int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+  interior = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 &&
+             (g.dim == 2 || (gz != 0 && gz != g.nn[2] - 1));
+  return ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
+}
+
+__device__ inline bool in_colour(const GeomDesc& g, int cx, int cy, int cz, int colour) {
+  int ox = colour % 3, oy = (colour / 3) % 3, oz = colour / 9;
+  return (cx % 3) == ox && (cy % 3) == oy && (g.dim == 2 || (cz % 3) == oz);
+}
+
+// x[plane t][node(K, b)] = val for every cell K of the colour, both planes
+__global__ void k_probe_set(GeomDesc g, int colour, int b, double val, double* x) {
+  for (long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x; cell < g.ncells;
+       cell += (long long)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    cell_coords(cell, g, cx, cy, cz);
+    if (!in_colour(g, cx, cy, cz, colour)) continue;
+    bool in;
+    long long node = node_of(g, cx, cy, cz, b, in);
+    x[node] = val;
+    x[g.nx + node] = val;
+  }
+}
+
+// column b of the principal blocks of every cell of the colour (column-major n_s x n_s)
+__global__ void k_extract(GeomDesc g, int colour, int b, const double* y, double* Ablk, double* Mblk) {
+  const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
+  long long total = g.ncells * ns;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long cell = idx / ns;
+    int a = (int)(idx - cell * ns);
+    int cx, cy, cz;
+    cell_coords(cell, g, cx, cy, cz);
+    if (!in_colour(g, cx, cy, cz, colour)) continue;
+    bool ina, inb;
+    long long na = node_of(g, cx, cy, cz, a, ina);
+    (void)node_of(g, cx, cy, cz, b, inb);
+    double av, mv;
+    if (!ina || !inb) {
+      av = mv = (a == b) ? 1.0 : 0.0;     // Dirichlet node: decoupled identity row/column
+    } else {
+      av = y[na];
+      mv = y[g.nx + na];
+    }
+    size_t off = (size_t)cell * ns * ns + (size_t)b * ns + a;
+    Ablk[off] = av;
+    Mblk[off] = mv;
+  }
+}
+
+// Tinv[K][s] = (lambda_{K,s} M_tau + N~)^{-1}, Gauss-Jordan with partial pivoting per thread
+template <class T>
+__global__ void k_tinv(long long ncells, int ns, int nt, const double* __restrict__ lam,
+                       const double* __restrict__ Mtau, const double* __restrict__ Nt, T* Tinv,
+                       int* bad) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < ncells * ns;
+       idx += (long long)gridDim.x * blockDim.x) {
+    double l = lam[idx];
+    double A[6][12];
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) {
+        A[i][j] = l * Mtau[i * nt + j] + Nt[i * nt + j];
+        A[i][nt + j] = (i == j) ? 1.0 : 0.0;
+      }
+    for (int c = 0; c < nt; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < nt; ++r)
+        if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
+      if (A[pr][c] == 0.0) { *bad = 1; break; }
+      if (pr != c)
+        for (int j = 0; j < 2 * nt; ++j) { double tmp = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = tmp; }
+      double d = 1.0 / A[c][c];
+      for (int j = 0; j < 2 * nt; ++j) A[c][j] *= d;
+      for (int r = 0; r < nt; ++r) {
+        if (r == c) continue;
+        double f = A[r][c];
+        for (int j = 0; j < 2 * nt; ++j) A[r][j] -= f * A[c][j];
+      }
+    }
+    T* out = Tinv + idx * nt * nt;
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) out[i * nt + j] = (T)A[i][nt + j];
+  }
+}
+
+template <class Tin, class Tout>
+__global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (Tout)a[i];
+}
+
+constexpr int ABS = 256;   // threads per workgroup of the apply kernel
+constexpr int JMAX = 32;   // accumulators per thread
+
+// u += omega * sum_K R_K^T B_K^{-1} R_K r   (interior rows; one workgroup per spatial cell)
+template <class T>
+__global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, int n_t, int nt_cell,
+                                                   const T* __restrict__ Q, const T* __restrict__ Tinv,
+                                                   const T* __restrict__ r, T* __restrict__ u, T omega,
+                                                   int nblocks) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
+  T* R = reinterpret_cast<T*>(smem_raw);     // [n_t][ns]
+  T* W = R + (size_t)n_t * ns;               // [n_t][ns]
+  const long long cell = xcd_swizzle(blockIdx.x, nblocks);
+  if (cell >= g.ncells) return;
+  int cx, cy, cz;
+  cell_coords(cell, g, cx, cy, cz);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n_t * ns; idx += ABS) {
+    int j = idx / ns, a = idx - j * ns;
+    bool in;
+    long long node = node_of(g, cx, cy, cz, a, in);
+    R[idx] = in ? r[(long long)j * g.nx + node] : (T)0;
+  }
+  __syncthreads();
+  const T* Qc = Q + (size_t)cell * ns * ns;     // column-major: Q(a, s) = Qc[s * ns + a]
+  const int JG = ABS / ns > 0 ? ABS / ns : 1;  // j-groups
+  const int o = tid % ns, jg = tid / ns;
+  const bool on = jg < JG && tid < JG * ns;
+  // W[j][s] = sum_a Q(a, s) R[j][a]   (this thread: s = o, j = jg + jj * JG)
+  if (on) {
+    T acc[JMAX];
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) acc[jj] = 0;
+    const T* qcol = Qc + (size_t)o * ns;
+    for (int a = 0; a < ns; ++a) {
+      T q = qcol[a];
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        int j = jg + jj * JG;
+        if (j < n_t) acc[jj] += q * R[j * ns + a];
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) {
+      int j = jg + jj * JG;
+      if (j < n_t) W[j * ns + o] = acc[jj];
+    }
+  }
+  __syncthreads();
+  // per mode s and time cell m: W[m, :, s] <- (lambda_s M_tau + N~)^{-1} W[m, :, s]
+  const int c = n_t / nt_cell;
+  for (int idx = tid; idx < c * ns; idx += ABS) {
+    int m = idx / ns, s = idx - m * ns;
+    const T* Ti = Tinv + ((size_t)cell * ns + s) * nt_cell * nt_cell;
+    T w[8], v[8];
+    for (int b = 0; b < nt_cell; ++b) w[b] = W[(m * nt_cell + b) * ns + s];
+    for (int a = 0; a < nt_cell; ++a) {
+      T acc = 0;
+      for (int b = 0; b < nt_cell; ++b) acc += Ti[a * nt_cell + b] * w[b];
+      v[a] = acc;
+    }
+    for (int a = 0; a < nt_cell; ++a) W[(m * nt_cell + a) * ns + s] = v[a];
+  }
+  __syncthreads();
+  // Z[j][a] = sum_s Q(a, s) W[j][s]; scatter-add omega * Z to the interior nodes
+  if (on) {
+    T acc[JMAX];
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) acc[jj] = 0;
+    for (int s = 0; s < ns; ++s) {
+      T q = Qc[(size_t)s * ns + o];
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        int j = jg + jj * JG;
+        if (j < n_t) acc[jj] += q * W[j * ns + s];
+      }
+    }
+    bool in;
+    long long node = node_of(g, cx, cy, cz, o, in);
+    if (in) {
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        int j = jg + jj * JG;
+        if (j < n_t) atomic_add(u + (long long)j * g.nx + node, omega * acc[jj]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void asm_probe_set(const GeomDesc& g, int colour, int b, double val, double* x, hipStream_t s) {
+  unsigned grid = ceil_div(g.ncells, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_probe_set, dim3(grid), dim3(256), 0, s, g, colour, b, val, x);
+  STMG_CHECK_LAUNCH();
+}
+
+void asm_extract(const GeomDesc& g, int colour, int b, const double* y, double* Ablk, double* Mblk,
+                 hipStream_t s) {
+  int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
+  unsigned grid = ceil_div(g.ncells * ns, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_extract, dim3(grid), dim3(256), 0, s, g, colour, b, y, Ablk, Mblk);
+  STMG_CHECK_LAUNCH();
+}
+
+template <class T>
+void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double* Mtau, const double* Nt,
+              T* Tinv, int* bad, hipStream_t s) {
+  unsigned grid = ceil_div(ncells * ns, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_tinv<T>, dim3(grid), dim3(256), 0, s, ncells, ns, nt, lam, Mtau, Nt, Tinv, bad);
+  STMG_CHECK_LAUNCH();
+}
+
+template <class Tout>
+void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s) {
+  unsigned grid = ceil_div(n, 256);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL((k_convert<double, Tout>), dim3(grid), dim3(256), 0, s, a, b, n);
+  STMG_CHECK_LAUNCH();
+}
+
+template <class T>
+void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
+               T omega, hipStream_t s) {
+  int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
+  int JG = ABS / ns > 0 ? ABS / ns : 1;
+  if ((n_t + JG - 1) / JG > JMAX) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the smoother kernel");
+  if (nt_cell > 8) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs per time cell");
+  size_t lds = sizeof(T) * 2 * (size_t)n_t * ns;
+  int nb = (int)g.ncells;
+  hipLaunchKernelGGL(k_asm_apply<T>, dim3(nb), dim3(ABS), lds, s, g, n_t, nt_cell, Q, Tinv, r, u, omega, nb);
+  STMG_CHECK_LAUNCH();
+}
+
+template void asm_tinv<double>(long long, int, int, const double*, const double*, const double*, double*, int*, hipStream_t);
+template void asm_tinv<float>(long long, int, int, const double*, const double*, const double*, float*, int*, hipStream_t);
+template void convert_from_double<float>(const double*, float*, long long, hipStream_t);
+template void convert_from_double<double>(const double*, double*, long long, hipStream_t);
+template void asm_apply<double>(const GeomDesc&, int, int, const double*, const double*, const double*,
+                                double*, double, hipStream_t);
+template void asm_apply<float>(const GeomDesc&, int, int, const float*, const float*, const float*, float*,
+                               float, hipStream_t);
+
+}  // namespace stmg

@@ -1,0 +1,222 @@
+// Vector kernels of the Krylov solver and the V-cycle (BLAS-1 style, HBM bound):
+// fills, copies, axpy, casts, Dirichlet-node updates, and fused multi-vector dot
+// products / updates for the Gram-Schmidt passes of FGMRES.  Reductions are two
+// stage (fixed grid of partial sums, then one block per result) so results do not
+// depend on atomics ordering.
+#include "kernels.hpp"
+
+namespace stmg {
+
+namespace {
+
+constexpr int BS = 256;
+
+inline unsigned grid_for(long long n) {
+  long long g = (n + BS - 1) / BS;
+  if (g > 65536) g = 65536;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+template <class T> __global__ void k_fill(T* y, T v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = v;
+}
+template <class T> __global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = x[i];
+}
+template <class T> __global__ void k_axpy(T a, const T* __restrict__ x, T* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] += a * x[i];
+}
+template <class T> __global__ void k_axpby(T a, const T* __restrict__ x, T b, T* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = a * x[i] + b * y[i];
+}
+template <class T> __global__ void k_scal(T a, T* y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] *= a;
+}
+__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = (float)x[i];
+}
+__global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) y[i] = (double)x[i];
+}
+template <class T>
+__global__ void k_boundary(const int* __restrict__ bidx, long long nb, long long nx, int n_t, T a,
+                           const T* __restrict__ x, T c, T* __restrict__ y) {
+  long long tot = nb * n_t;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+    long long t = i / nb, j = i - t * nb;
+    long long g = t * nx + bidx[j];
+    y[g] = a * x[g] + c * y[g];
+  }
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+// partial dots of up to JC vectors against w: part[block * JC + j]
+__global__ void k_dot_part(const double* __restrict__ V, long long ldv, int kc,
+                           const double* __restrict__ w, long long n, double* __restrict__ part) {
+  __shared__ double sh[BS / 64];
+  double acc[JC];
+#pragma unroll
+  for (int j = 0; j < JC; ++j) acc[j] = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < JC; ++j)
+      if (j < kc) acc[j] += V[j * ldv + i] * wi;
+  }
+  for (int j = 0; j < kc; ++j) {
+    double s = block_sum(acc[j], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * JC + j] = s;
+  }
+}
+
+__global__ void k_dot_final(const double* __restrict__ part, int nblocks, int kc, double* out) {
+  __shared__ double sh[BS / 64];
+  int j = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[b * JC + j];
+  double s = block_sum(v, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+__global__ void k_multi_axpy_neg(const double* __restrict__ V, long long ldv, int k,
+                                 const double* __restrict__ h, double* __restrict__ w, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double s = w[i];
+    for (int j = 0; j < k; ++j) s -= h[j] * V[j * ldv + i];
+    w[i] = s;
+  }
+}
+
+template <class T>
+__global__ void k_multi_axpy_acc(const T* __restrict__ Z, long long ldz, int k,
+                                 const double* __restrict__ y, double* __restrict__ x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += y[j] * (double)Z[j * ldz + i];
+    x[i] = s;
+  }
+}
+
+template <class T>
+__global__ void k_norm_part(const T* __restrict__ x, long long n, double* part) {
+  __shared__ double sh[BS / 64];
+  double acc = 0.0, bad = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double v = (double)x[i];
+    if (!isfinite(v)) bad = 1.0;
+    else acc += v * v;
+  }
+  double s = block_sum(acc, sh);
+  double b = block_sum(bad, sh);
+  if (threadIdx.x == 0) { part[blockIdx.x * JC] = s; part[blockIdx.x * JC + 1] = b; }
+}
+
+}  // namespace
+
+template <class T> void fill(T* y, T v, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(BS), 0, s, y, v, n);
+  STMG_CHECK_LAUNCH();
+}
+template <class T> void copy(const T* x, T* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+  STMG_CHECK_LAUNCH();
+}
+template <class T> void axpy(T a, const T* x, T* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy<T>, dim3(grid_for(n)), dim3(BS), 0, s, a, x, y, n);
+  STMG_CHECK_LAUNCH();
+}
+template <class T> void axpby(T a, const T* x, T b, T* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(BS), 0, s, a, x, b, y, n);
+  STMG_CHECK_LAUNCH();
+}
+template <class T> void scal(T a, T* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scal<T>, dim3(grid_for(n)), dim3(BS), 0, s, a, y, n);
+  STMG_CHECK_LAUNCH();
+}
+void cast_d2f(const double* x, float* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+  STMG_CHECK_LAUNCH();
+}
+void cast_f2d(const float* x, double* y, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_f2d, dim3(grid_for(n)), dim3(BS), 0, s, x, y, n);
+  STMG_CHECK_LAUNCH();
+}
+template <class T>
+void boundary_axpby(const int* bidx, long long nb, long long nx, int n_t, T a, const T* x, T c, T* y,
+                    hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_boundary<T>, dim3(grid_for(nb * n_t)), dim3(BS), 0, s, bidx, nb, nx, n_t, a, x, c, y);
+  STMG_CHECK_LAUNCH();
+}
+
+void multi_dot(const double* V, long long ldv, int k, const double* w, long long n, double* out,
+               double* part, hipStream_t s) {
+  unsigned nb = grid_for(n);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  for (int j0 = 0; j0 < k; j0 += JC) {
+    int kc = k - j0 < JC ? k - j0 : JC;
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(BS), 0, s, V + j0 * ldv, ldv, kc, w, n, part);
+    STMG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_dot_final, dim3(kc), dim3(BS), 0, s, part, (int)nb, kc, out + j0);
+    STMG_CHECK_LAUNCH();
+  }
+}
+
+void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, double* w, long long n,
+                    hipStream_t s) {
+  if (n <= 0 || k <= 0) return;
+  hipLaunchKernelGGL(k_multi_axpy_neg, dim3(grid_for(n)), dim3(BS), 0, s, V, ldv, k, h, w, n);
+  STMG_CHECK_LAUNCH();
+}
+
+template <class T>
+void multi_axpy_acc(const T* Z, long long ldz, int k, const double* y, double* x, long long n,
+                    hipStream_t s) {
+  if (n <= 0 || k <= 0) return;
+  hipLaunchKernelGGL(k_multi_axpy_acc<T>, dim3(grid_for(n)), dim3(BS), 0, s, Z, ldz, k, y, x, n);
+  STMG_CHECK_LAUNCH();
+}
+
+template <class T> void norm2_check(const T* x, long long n, double* out, double* part, hipStream_t s) {
+  unsigned nb = grid_for(n);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), dim3(BS), 0, s, x, n, part);
+  STMG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_dot_final, dim3(2), dim3(BS), 0, s, part, (int)nb, 2, out);
+  STMG_CHECK_LAUNCH();
+}
+
+#define INST(T)                                                                                   \
+  template void fill<T>(T*, T, long long, hipStream_t);                                            \
+  template void copy<T>(const T*, T*, long long, hipStream_t);                                     \
+  template void axpy<T>(T, const T*, T*, long long, hipStream_t);                                  \
+  template void axpby<T>(T, const T*, T, T*, long long, hipStream_t);                              \
+  template void scal<T>(T, T*, long long, hipStream_t);                                            \
+  template void boundary_axpby<T>(const int*, long long, long long, int, T, const T*, T, T*,      \
+                                  hipStream_t);                                                    \
+  template void multi_axpy_acc<T>(const T*, long long, int, const double*, double*, long long,    \
+                                  hipStream_t);                                                    \
+  template void norm2_check<T>(const T*, long long, double*, double*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace stmg

@@ -1,0 +1,53 @@
+// Device-side descriptors shared by the kernels: one level's spatial
+// discretisation and the slab's temporal factors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace stmg {
+
+constexpr int MAXN = 5;   // p + 1 <= 5
+
+// Spatial discretisation of one level (lattice of Q_p cells).
+struct GeomDesc {
+  int dim = 3, p = 1, n = 2;
+  int nc[3] = {1, 1, 1};   // cells per direction
+  int nn[3] = {1, 1, 1};   // nodes per direction
+  long long nx = 1;        // nodes per temporal plane
+  long long ncells = 1;
+  const double* verts = nullptr;   // vertex lattice (nc+1)^dim x dim, or null (Cartesian)
+  double lo[3] = {0, 0, 0}, h[3] = {1, 1, 1};
+  const double* rho = nullptr;     // per cell, or per (cell, quadrature point) if rho_q
+  int rho_q = 0;
+};
+
+// Slab temporal factors in CSR form (rows i, columns j), device pointers.
+template <class T>
+struct TemporalDev {
+  int n_t = 0;
+  const int* mptr = nullptr; const int* mcol = nullptr; const T* mval = nullptr;
+  const int* nptr = nullptr; const int* ncol = nullptr; const T* nval = nullptr;
+};
+
+// 1D tables of Q_p with GLL nodes at the (p+1)-point Gauss rule:
+// S[q][i] = l_i(xi_q), D[q][r] = l^G_r'(xi_q) (collocation derivative on the Gauss points).
+template <class T, int N>
+struct Tables {
+  T S[N][N];
+  T D[N][N];
+  double gq[N];   // Gauss points on [0, 1]
+  double gw[N];   // Gauss weights
+};
+
+// XCD-aware block order: consecutive logical blocks land on the same XCD
+// (hardware dispatches workgroups round-robin over the 8 XCDs).
+__device__ inline int xcd_swizzle(int b, int nb) {
+  int per = nb >> 3, rem = nb & 7, xcd = b & 7, idx = b >> 3;
+  return (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <class T> __device__ inline void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace stmg

@@ -1,0 +1,104 @@
+// The library handle: level hierarchy (Section 4, Alg. mg-sequence with spatial
+// levels), per-precision V-cycle data, and the FP64 FGMRES workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "hostmath.hpp"
+#include "kernels.hpp"
+
+namespace stmg {
+
+struct Transfer1D {           // one direction of P (coarse -> fine) or R = P^T (fine -> coarse)
+  int len_out = 0;
+  DevBuf ptr, col, w64, w32;
+};
+
+template <class T>
+struct LevelData {            // precision-dependent data of one level
+  DevBuf Q, Tinv;             // smoother factors (not on the coarsest level)
+  DevBuf u, r, f, tmpA, tmpB; // V-cycle work vectors
+  DevBuf Cinv;                // coarsest level only: dense inverse on interior DoFs
+};
+
+struct Level {
+  int p = 1;
+  int cells[3] = {1, 1, 1};
+  int ratio = 1;              // finest cells per cell of this level, per direction
+  GeomDesc g;
+  LevelTables lt;
+  DevBuf verts, rho, bidx, mask;
+  long long nb = 0;           // boundary nodes per temporal plane
+  long long n_int = 0;        // interior nodes per temporal plane
+  double omega = 1.0;
+  // transfer between this level (fine) and level+1 (coarse)
+  std::array<Transfer1D, 3> P, R;
+  // coarsest level
+  DevBuf cidx;                // interior DoF indices (full-lattice space-time index)
+  int cm = 0;
+  LevelData<double> d64;
+  LevelData<float> d32;
+  bool has64 = false, has32 = false;
+  long long nst(int n_t) const { return g.nx * n_t; }
+};
+
+template <class T>
+struct TemporalBufs {
+  DevBuf mptr, mcol, mval, nptr, ncol, nval;
+  TemporalDev<T> dev;
+};
+
+struct Timer {               // event-based bucket timer for stmg_solve
+  std::vector<hipEvent_t> ev;
+  std::vector<int> tag;
+  size_t used = 0;
+  bool on = false;
+  void mark(int t, hipStream_t s);
+  void reset() { used = 0; }
+  void accumulate(double out[4]);
+  ~Timer();
+};
+enum { TB_SMOOTH = 0, TB_GMG = 1, TB_OP = 2, TB_OTHER = 3 };
+
+struct CnnState;              // learned stage (cnn.hip)
+void cnn_free(CnnState* c);
+
+}  // namespace stmg
+
+struct stmg_handle {
+  stmg_config cfg;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  stmg::hm::Temporal tm;
+  stmg::TemporalBufs<double> tp64;
+  stmg::TemporalBufs<float> tp32;
+  std::vector<std::unique_ptr<stmg::Level>> levels;
+  bool want64 = true, want32 = false;
+  // FGMRES workspace (finest level)
+  stmg::DevBuf V, Z64, Z32, w, tmp32a, tmp32b, dots, red, hbuf;
+  int krylov_m = 0;
+  stmg::Timer timer;
+  double setup_seconds = 0.0;
+  int64_t bytes_at_create = 0;
+  stmg::CnnState* cnn = nullptr;
+  ~stmg_handle();
+};
+
+namespace stmg {
+// set-up and V-cycle entry points used by the C ABI (hierarchy.hip)
+void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff);
+template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y);
+template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int steps);
+template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u);
+template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T* fine, bool accumulate);
+template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* coarse);
+void estimate_omegas(stmg_handle* h);
+stmg_status fgmres(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
+template <class T> LevelData<T>& ldata(Level& L);
+template <class T> const TemporalDev<T>& tdev(stmg_handle* h);
+}  // namespace stmg

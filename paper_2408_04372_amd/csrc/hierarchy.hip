@@ -1,0 +1,671 @@
+// Level hierarchy, smoother set-up, relaxation estimates and the V-cycle
+// (Section 4: Alg. stmg and Alg. mg-sequence, spatial levels only).
+//
+// Level sequence (finest first): halve p while p > min_p, then halve the cell
+// count per direction while every direction stays even and does not drop below
+// coarse_cells.  Coarse h-levels take the even-index vertex subset and
+// re-discretise; their coefficient at a quadrature point is that of the finest
+// descendant cell whose reference sub-box contains the point.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "handle.hpp"
+
+namespace stmg {
+
+template <> LevelData<double>& ldata<double>(Level& L) { return L.d64; }
+template <> LevelData<float>& ldata<float>(Level& L) { return L.d32; }
+template <> const TemporalDev<double>& tdev<double>(stmg_handle* h) { return h->tp64.dev; }
+template <> const TemporalDev<float>& tdev<float>(stmg_handle* h) { return h->tp32.dev; }
+
+// ------------------------------------------------------------------ timer
+void Timer::mark(int t, hipStream_t s) {
+  if (!on) return;
+  if (used == ev.size()) {
+    hipEvent_t e;
+    STMG_HIP(hipEventCreate(&e));
+    ev.push_back(e);
+    tag.push_back(0);
+  }
+  tag[used] = t;
+  STMG_HIP(hipEventRecord(ev[used], s));
+  ++used;
+}
+void Timer::accumulate(double out[4]) {
+  if (used < 2) return;
+  STMG_HIP(hipEventSynchronize(ev[used - 1]));
+  for (size_t i = 0; i + 1 < used; ++i) {
+    float ms = 0.f;
+    STMG_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    out[tag[i]] += ms * 1e-3;
+  }
+}
+Timer::~Timer() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------------ 1D tables
+LevelTables make_level_tables(int p) {
+  LevelTables t;
+  int n = p + 1;
+  t.n = n;
+  hm::Vec gq, gw;
+  hm::gauss(n, gq, gw);
+  hm::Vec nodes = hm::gauss_lobatto(n);
+  hm::Mat V, D, Vg, Dg;
+  hm::lagrange(nodes, gq, V, D);      // GLL basis at Gauss points
+  hm::lagrange(gq, gq, Vg, Dg);       // Gauss-point Lagrange basis: collocation derivative
+  t.S.assign(V.a.begin(), V.a.end());
+  t.D.assign(Dg.a.begin(), Dg.a.end());
+  t.gq = gq;
+  t.gw = gw;
+  return t;
+}
+
+namespace {
+
+// CSR of the nonzeros of a dense n x n matrix
+template <class T>
+void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s) {
+  std::vector<int> p{0}, c;
+  std::vector<T> v;
+  for (int i = 0; i < A.r; ++i) {
+    for (int j = 0; j < A.c; ++j)
+      if (A(i, j) != 0.0) { c.push_back(j); v.push_back((T)A(i, j)); }
+    p.push_back((int)c.size());
+  }
+  if (c.empty()) { c.push_back(0); v.push_back(0); }
+  ptr = upload(p, s);
+  col = upload(c, s);
+  val = upload(v, s);
+}
+
+template <class T>
+void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {
+  upload_csr<T>(tm.M_T, tb.mptr, tb.mcol, tb.mval, s);
+  upload_csr<T>(tm.N_T, tb.nptr, tb.ncol, tb.nval, s);
+  tb.dev.n_t = tm.n_t;
+  tb.dev.mptr = tb.mptr.template as<int>(); tb.dev.mcol = tb.mcol.template as<int>(); tb.dev.mval = tb.mval.template as<T>();
+  tb.dev.nptr = tb.nptr.template as<int>(); tb.dev.ncol = tb.ncol.template as<int>(); tb.dev.nval = tb.nval.template as<T>();
+}
+
+// 1D prolongation from a coarse (pc, ncc cells) to a fine (pf, ncf cells) lattice along one axis
+void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R, hipStream_t s) {
+  int r = ncf / ncc;
+  int Nf = pf * ncf + 1, Nc = pc * ncc + 1;
+  hm::Vec fn = hm::gauss_lobatto(pf + 1), cn = hm::gauss_lobatto(pc + 1);
+  std::vector<std::vector<std::pair<int, double>>> rows(Nf), cols(Nc);
+  for (int g = 0; g < Nf; ++g) {
+    int cf = std::min(g / pf, ncf - 1);
+    int lf = g - cf * pf;
+    int cc = cf / r;
+    double xi = ((cf - cc * r) + fn[lf]) / r;
+    hm::Mat V, D;
+    hm::lagrange(cn, hm::Vec{xi}, V, D);
+    for (int j = 0; j <= pc; ++j) {
+      double w = V(0, j);
+      if (std::fabs(w) < 1e-14) continue;
+      rows[g].push_back({cc * pc + j, w});
+      cols[cc * pc + j].push_back({g, w});
+    }
+  }
+  auto up = [&](const std::vector<std::vector<std::pair<int, double>>>& L, Transfer1D& T) {
+    std::vector<int> ptr{0}, col;
+    std::vector<double> w;
+    std::vector<float> wf;
+    for (auto& row : L) {
+      for (auto& e : row) { col.push_back(e.first); w.push_back(e.second); wf.push_back((float)e.second); }
+      ptr.push_back((int)col.size());
+    }
+    T.len_out = (int)L.size();
+    T.ptr = upload(ptr, s);
+    T.col = upload(col, s);
+    T.w64 = upload(w, s);
+    T.w32 = upload(wf, s);
+  };
+  up(rows, P);
+  up(cols, R);
+}
+
+void init_geom(Level& L, int dim, const stmg_config& cfg) {
+  GeomDesc& g = L.g;
+  g.dim = dim;
+  g.p = L.p;
+  g.n = L.p + 1;
+  g.nx = 1;
+  g.ncells = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.nc[d] = d < dim ? L.cells[d] : 1;
+    g.nn[d] = d < dim ? L.p * L.cells[d] + 1 : 1;
+    g.nx *= g.nn[d];
+    g.ncells *= g.nc[d];
+    g.lo[d] = cfg.lo[d];
+    g.h[d] = d < dim ? (cfg.hi[d] - cfg.lo[d]) / L.cells[d] : 1.0;
+  }
+}
+
+void boundary_lists(Level& L, hipStream_t s) {
+  const GeomDesc& g = L.g;
+  std::vector<int> b;
+  std::vector<unsigned char> m(g.nx);
+  for (long long z = 0; z < g.nn[2]; ++z)
+    for (long long y = 0; y < g.nn[1]; ++y)
+      for (long long x = 0; x < g.nn[0]; ++x) {
+        long long idx = (z * g.nn[1] + y) * g.nn[0] + x;
+        bool bd = x == 0 || x == g.nn[0] - 1 || y == 0 || y == g.nn[1] - 1 ||
+                  (g.dim == 3 && (z == 0 || z == g.nn[2] - 1));
+        m[idx] = bd ? 0 : 1;
+        if (bd) b.push_back((int)idx);
+      }
+  L.nb = (long long)b.size();
+  L.n_int = g.nx - L.nb;
+  L.bidx = upload(b, s);
+  L.mask = upload(m, s);
+}
+
+// coefficient data of a level: per cell on the finest mesh, per quadrature point on coarse h-levels
+void level_coefficients(Level& L, const std::vector<double>& coef_fine, const int fine_cells[3],
+                        hipStream_t s) {
+  const GeomDesc& g = L.g;
+  if (L.ratio == 1) {
+    L.rho = upload(coef_fine, s);
+    L.g.rho_q = 0;
+  } else {
+    int n = g.n;
+    int nq = g.dim == 3 ? n * n * n : n * n;
+    std::vector<double> rq((size_t)g.ncells * nq);
+    for (long long c = 0; c < g.ncells; ++c) {
+      long long cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / ((long long)g.nc[0] * g.nc[1]);
+      for (int q = 0; q < nq; ++q) {
+        int qi[3] = {q % n, (q / n) % n, q / (n * n)};
+        long long fc[3] = {cx, cy, cz};
+        for (int d = 0; d < g.dim; ++d) {
+          long long sub = (long long)std::floor(L.lt.gq[qi[d]] * L.ratio);
+          if (sub > L.ratio - 1) sub = L.ratio - 1;
+          fc[d] = fc[d] * L.ratio + sub;
+        }
+        long long fidx = fc[0] + (long long)fine_cells[0] * (fc[1] + (g.dim == 3 ? (long long)fine_cells[1] * fc[2] : 0));
+        rq[(size_t)c * nq + q] = coef_fine[fidx];
+      }
+    }
+    L.rho = upload(rq, s);
+    L.g.rho_q = 1;
+  }
+  L.g.rho = L.rho.as<double>();
+}
+
+// principal blocks A_KK, M_KK by probing the matrix-free operator, then the generalised
+// eigenproblem A Q = M Q Lambda (rocSOLVER, batched) and the per-mode temporal inverses
+void setup_smoother(stmg_handle* h, Level& L) {
+  hipStream_t s = h->stream;
+  const GeomDesc& g = L.g;
+  const int ns = g.dim == 3 ? g.n * g.n * g.n : g.n * g.n;
+  const long long nblk = g.ncells * ns * ns;
+  DevBuf A(sizeof(double) * nblk), M(sizeof(double) * nblk);
+  DevBuf x2(sizeof(double) * 2 * g.nx), y2(sizeof(double) * 2 * g.nx);
+  // two-plane operator: plane 0 -> A_h x, plane 1 -> M_h x
+  hm::Mat Mp(2, 2), Np(2, 2);
+  Mp(0, 0) = 1.0;
+  Np(1, 1) = 1.0;
+  DevBuf mp, mc, mv, np_, nc, nv;
+  upload_csr<double>(Mp, mp, mc, mv, s);
+  upload_csr<double>(Np, np_, nc, nv, s);
+  TemporalDev<double> tp2;
+  tp2.n_t = 2;
+  tp2.mptr = mp.as<int>(); tp2.mcol = mc.as<int>(); tp2.mval = mv.as<double>();
+  tp2.nptr = np_.as<int>(); tp2.ncol = nc.as<int>(); tp2.nval = nv.as<double>();
+  const int ncol = g.dim == 3 ? 27 : 9;
+  fill<double>(x2.as<double>(), 0.0, 2 * g.nx, s);
+  for (int colour = 0; colour < ncol; ++colour)
+    for (int b = 0; b < ns; ++b) {
+      asm_probe_set(g, colour, b, 1.0, x2.as<double>(), s);
+      fill<double>(y2.as<double>(), 0.0, 2 * g.nx, s);
+      st_apply<double>(g, L.lt, tp2, x2.as<double>(), y2.as<double>(), 1.0, s);
+      asm_extract(g, colour, b, y2.as<double>(), A.as<double>(), M.as<double>(), s);
+      asm_probe_set(g, colour, b, 0.0, x2.as<double>(), s);
+    }
+  x2.release();
+  y2.release();
+  DevBuf lam(sizeof(double) * g.ncells * ns), E(sizeof(double) * g.ncells * ns),
+      info(sizeof(int) * g.ncells);
+  rocblas_handle rb;
+  if (rocblas_create_handle(&rb) != rocblas_status_success) fail(STMG_E_HIP, "rocblas_create_handle failed");
+  rocblas_set_stream(rb, s);
+  rocblas_status st = rocsolver_dsygvd_strided_batched(
+      rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, A.as<double>(), ns,
+      (rocblas_stride)ns * ns, M.as<double>(), ns, (rocblas_stride)ns * ns, lam.as<double>(), ns,
+      E.as<double>(), ns, info.as<int>(), (int)g.ncells);
+  STMG_HIP(hipStreamSynchronize(s));
+  rocblas_destroy_handle(rb);
+  if (st != rocblas_status_success) fail(STMG_E_HIP, "rocsolver_dsygvd_strided_batched failed");
+  std::vector<int> inf = download<int>(info.get(), g.ncells, s);
+  for (long long c = 0; c < g.ncells; ++c)
+    if (inf[c] != 0) fail(STMG_E_ARG, "local smoother block is not positive definite (cell " + std::to_string(c) + ")");
+  M.release();
+  E.release();
+  int nt = h->tm.nt_cell;
+  DevBuf Mt = upload(h->tm.M_tau.a, s), Nt = upload(h->tm.N_tilde.a, s), bad(sizeof(int));
+  STMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
+  if (L.has32) {
+    L.d32.Q.alloc(sizeof(float) * nblk);
+    convert_from_double<float>(A.as<double>(), L.d32.Q.as<float>(), nblk, s);
+    L.d32.Tinv.alloc(sizeof(float) * g.ncells * ns * nt * nt);
+    asm_tinv<float>(g.ncells, ns, nt, lam.as<double>(), Mt.as<double>(), Nt.as<double>(),
+                    L.d32.Tinv.as<float>(), bad.as<int>(), s);
+  }
+  if (L.has64) {
+    L.d64.Tinv.alloc(sizeof(double) * g.ncells * ns * nt * nt);
+    asm_tinv<double>(g.ncells, ns, nt, lam.as<double>(), Mt.as<double>(), Nt.as<double>(),
+                     L.d64.Tinv.as<double>(), bad.as<int>(), s);
+    L.d64.Q = std::move(A);
+  }
+  std::vector<int> b = download<int>(bad.get(), 1, s);
+  if (b[0]) fail(STMG_E_ARG, "singular temporal block in the smoother set-up");
+}
+
+template <class T>
+void alloc_work(Level& L, int n_t, bool coarsest) {
+  LevelData<T>& d = ldata<T>(L);
+  size_t n = (size_t)L.g.nx * n_t * sizeof(T);
+  d.u.alloc(n);
+  d.r.alloc(n);
+  d.f.alloc(n);
+  if (!coarsest) {
+    d.tmpA.alloc(n);
+    d.tmpB.alloc(n);
+  }
+}
+
+// coarsest level: probe the interior operator column by column, invert on the host
+void setup_coarse(stmg_handle* h, Level& L) {
+  hipStream_t s = h->stream;
+  int n_t = h->tm.n_t;
+  std::vector<unsigned char> mask = download<unsigned char>(L.mask.get(), L.g.nx, s);
+  std::vector<long long> idx;
+  for (int t = 0; t < n_t; ++t)
+    for (long long gnode = 0; gnode < L.g.nx; ++gnode)
+      if (mask[gnode]) idx.push_back((long long)t * L.g.nx + gnode);
+  int m = (int)idx.size();
+  if (m > 6000) fail(STMG_E_UNSUPPORTED, "coarsest level too large (" + std::to_string(m) + " unknowns); raise the cell count to a power of two or lower coarse_cells");
+  L.cm = m;
+  L.cidx = upload(idx, s);
+  if (m == 0) return;
+  size_t n = (size_t)L.g.nx * n_t;
+  DevBuf x(sizeof(double) * n), y(sizeof(double) * n);
+  hm::Mat C(m, m);
+  fill<double>(x.as<double>(), 0.0, n, s);
+  for (int j = 0; j < m; ++j) {
+    double one = 1.0, zero = 0.0;
+    STMG_HIP(hipMemcpyAsync(x.as<double>() + idx[j], &one, sizeof(double), hipMemcpyHostToDevice, s));
+    fill<double>(y.as<double>(), 0.0, n, s);
+    st_apply<double>(L.g, L.lt, h->tp64.dev, x.as<double>(), y.as<double>(), 1.0, s);
+    std::vector<double> col = download<double>(y.get(), n, s);
+    for (int i = 0; i < m; ++i) C(i, j) = col[idx[i]];
+    STMG_HIP(hipMemcpyAsync(x.as<double>() + idx[j], &zero, sizeof(double), hipMemcpyHostToDevice, s));
+    STMG_HIP(hipStreamSynchronize(s));
+  }
+  hm::Mat Ci = hm::inverse(C);
+  if (L.has64) L.d64.Cinv = upload(Ci.a, s);
+  if (L.has32) {
+    std::vector<float> f(Ci.a.begin(), Ci.a.end());
+    L.d32.Cinv = upload(f, s);
+  }
+  STMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff) {
+  const stmg_config& cfg = h->cfg;
+  hipStream_t s = h->stream;
+  int dim = cfg.dim;
+  h->tm = hm::temporal(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau);
+  make_temporal<double>(h->tm, h->tp64, s);
+  make_temporal<float>(h->tm, h->tp32, s);
+  int fine_cells[3] = {cfg.n_cells[0], cfg.n_cells[1], dim == 3 ? cfg.n_cells[2] : 1};
+  long long ncf = (long long)fine_cells[0] * fine_cells[1] * fine_cells[2];
+  std::vector<double> coef(ncf, 1.0);
+  if (coeff) {
+    for (long long c = 0; c < ncf; ++c) {
+      if (!(coeff[c] > 0.0) || !std::isfinite(coeff[c])) fail(STMG_E_ARG, "coefficients must be positive and finite");
+      coef[c] = coeff[c];
+    }
+  }
+  // level shapes
+  struct Shape { int p; int cells[3]; int ratio; };
+  std::vector<Shape> shapes;
+  Shape cur{cfg.p, {fine_cells[0], fine_cells[1], fine_cells[2]}, 1};
+  shapes.push_back(cur);
+  while (cur.p > cfg.min_p) {
+    cur.p = std::max(cfg.min_p, cur.p / 2);
+    shapes.push_back(cur);
+  }
+  for (;;) {
+    bool ok = true;
+    for (int d = 0; d < dim; ++d)
+      if (cur.cells[d] % 2 != 0 || cur.cells[d] / 2 < cfg.coarse_cells) ok = false;
+    if (!ok) break;
+    for (int d = 0; d < dim; ++d) cur.cells[d] /= 2;
+    cur.ratio *= 2;
+    shapes.push_back(cur);
+  }
+  if ((int)shapes.size() > STMG_MAX_LEVELS) fail(STMG_E_UNSUPPORTED, "too many levels");
+  std::vector<double> verts_host;
+  if (vertices) {
+    long long nv = 1;
+    for (int d = 0; d < dim; ++d) nv *= fine_cells[d] + 1;
+    verts_host.assign(vertices, vertices + nv * dim);
+  }
+  for (size_t l = 0; l < shapes.size(); ++l) {
+    auto L = std::make_unique<Level>();
+    L->p = shapes[l].p;
+    for (int d = 0; d < 3; ++d) L->cells[d] = shapes[l].cells[d];
+    L->ratio = shapes[l].ratio;
+    init_geom(*L, dim, cfg);
+    L->lt = make_level_tables(L->p);
+    if (vertices) {
+      // even-index subset of the finest vertex lattice
+      int r = L->ratio;
+      std::vector<double> v;
+      int vn[3] = {L->cells[0] + 1, L->cells[1] + 1, dim == 3 ? L->cells[2] + 1 : 1};
+      int fn[3] = {fine_cells[0] + 1, fine_cells[1] + 1, dim == 3 ? fine_cells[2] + 1 : 1};
+      v.reserve((size_t)vn[0] * vn[1] * vn[2] * dim);
+      for (int z = 0; z < vn[2]; ++z)
+        for (int y = 0; y < vn[1]; ++y)
+          for (int x = 0; x < vn[0]; ++x) {
+            size_t src = ((size_t)(z * r) * fn[1] + (size_t)y * r) * fn[0] + (size_t)x * r;
+            for (int d = 0; d < dim; ++d) v.push_back(verts_host[src * dim + d]);
+          }
+      L->verts = upload(v, s);
+      L->g.verts = L->verts.as<double>();
+    }
+    level_coefficients(*L, coef, fine_cells, s);
+    boundary_lists(*L, s);
+    L->has64 = h->want64;
+    L->has32 = h->want32;
+    h->levels.push_back(std::move(L));
+  }
+  // transfers: level l (fine) <- level l+1 (coarse)
+  for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
+    Level& F = *h->levels[l];
+    Level& C = *h->levels[l + 1];
+    for (int d = 0; d < dim; ++d) transfer_1d(C.p, C.cells[d], F.p, F.cells[d], F.P[d], F.R[d], s);
+  }
+  // smoothers, work vectors, coarse inverse
+  int n_t = h->tm.n_t;
+  for (size_t l = 0; l < h->levels.size(); ++l) {
+    Level& L = *h->levels[l];
+    bool coarsest = (l + 1 == h->levels.size());
+    if (L.has64) alloc_work<double>(L, n_t, coarsest);
+    if (L.has32) alloc_work<float>(L, n_t, coarsest);
+    if (!coarsest) setup_smoother(h, L);
+    else setup_coarse(h, L);
+  }
+  // relaxation
+  if (cfg.omega > 0.0) {
+    for (auto& L : h->levels) L->omega = cfg.omega;
+  } else {
+    estimate_omegas(h);
+  }
+  h->levels.back()->omega = 0.0;
+  STMG_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ level operations
+
+template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
+  Level& L = *h->levels[level];
+  hipStream_t s = h->stream;
+  long long n = L.nst(h->tm.n_t);
+  fill<T>(y, (T)0, n, s);
+  st_apply<T>(L.g, L.lt, tdev<T>(h), x, y, (T)1, s);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)1, x, (T)0, y, s);
+}
+
+// r = f - S u
+template <class T> static void residual(stmg_handle* h, Level& L, const T* f, const T* u, T* r) {
+  hipStream_t s = h->stream;
+  long long n = L.nst(h->tm.n_t);
+  copy<T>(f, r, n, s);
+  st_apply<T>(L.g, L.lt, tdev<T>(h), u, r, (T)-1, s);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)-1, u, (T)1, r, s);
+}
+
+// u += omega * ASM(r)
+template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u) {
+  LevelData<T>& d = ldata<T>(L);
+  h->timer.mark(TB_SMOOTH, h->stream);
+  asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
+               (T)L.omega, h->stream);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)L.omega, r, (T)1, u, h->stream);
+  h->timer.mark(TB_GMG, h->stream);
+}
+
+template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int steps) {
+  Level& L = *h->levels[level];
+  LevelData<T>& d = ldata<T>(L);
+  for (int i = 0; i < steps; ++i) {
+    residual<T>(h, L, b, x, d.r.template as<T>());
+    asm_step<T>(h, L, d.r.template as<T>(), x);
+  }
+}
+
+template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T* fine, bool accumulate) {
+  Level& F = *h->levels[level];
+  Level& C = *h->levels[level + 1];
+  LevelData<T>& d = ldata<T>(F);
+  hipStream_t s = h->stream;
+  int n_t = h->tm.n_t;
+  int dim = F.g.dim;
+  const T* in = coarse;
+  int dims[3] = {C.g.nn[0], C.g.nn[1], C.g.nn[2]};
+  T* bufs[2] = {d.tmpA.template as<T>(), d.tmpB.template as<T>()};
+  for (int ax = 0; ax < dim; ++ax) {
+    bool last = (ax == dim - 1);
+    T* out = last ? fine : bufs[ax & 1];
+    const Transfer1D& tr = F.P[ax];
+    const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w,
+               ax == 0 ? C.mask.as<unsigned char>() : nullptr,
+               last ? F.mask.as<unsigned char>() : nullptr, last && accumulate, s);
+    dims[ax] = tr.len_out;
+    in = out;
+  }
+}
+
+template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* coarse) {
+  Level& F = *h->levels[level];
+  Level& C = *h->levels[level + 1];
+  LevelData<T>& d = ldata<T>(F);
+  hipStream_t s = h->stream;
+  int n_t = h->tm.n_t;
+  int dim = F.g.dim;
+  const T* in = fine;
+  int dims[3] = {F.g.nn[0], F.g.nn[1], F.g.nn[2]};
+  T* bufs[2] = {d.tmpA.template as<T>(), d.tmpB.template as<T>()};
+  for (int ax = 0; ax < dim; ++ax) {
+    bool last = (ax == dim - 1);
+    T* out = last ? coarse : bufs[ax & 1];
+    const Transfer1D& tr = F.R[ax];
+    const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w,
+               ax == 0 ? F.mask.as<unsigned char>() : nullptr,
+               last ? C.mask.as<unsigned char>() : nullptr, false, s);
+    dims[ax] = tr.len_out;
+    in = out;
+  }
+}
+
+// Alg. stmg on level `level` with zero initial guess: u = V(f)
+template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u) {
+  Level& L = *h->levels[level];
+  LevelData<T>& d = ldata<T>(L);
+  hipStream_t s = h->stream;
+  int n_t = h->tm.n_t;
+  long long n = L.nst(n_t);
+  if (level + 1 == (int)h->levels.size()) {
+    coarse_apply<T>(d.Cinv.template as<T>(), L.cidx.as<long long>(), L.cm, f, u, s);
+    boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, n_t, (T)1, f, (T)0, u, s);
+    return;
+  }
+  const int nu = h->cfg.n_smooth;
+  // pre-smoothing from u = 0: the first step needs no residual
+  fill<T>(u, (T)0, n, s);
+  asm_step<T>(h, L, f, u);
+  for (int i = 1; i < nu; ++i) {
+    residual<T>(h, L, f, u, d.r.template as<T>());
+    asm_step<T>(h, L, d.r.template as<T>(), u);
+  }
+  residual<T>(h, L, f, u, d.r.template as<T>());
+  Level& C = *h->levels[level + 1];
+  LevelData<T>& dc = ldata<T>(C);
+  restrict_<T>(h, level, d.r.template as<T>(), dc.f.template as<T>());
+  vcycle<T>(h, level + 1, dc.f.template as<T>(), dc.u.template as<T>());
+  prolongate<T>(h, level, dc.u.template as<T>(), u, true);
+  for (int i = 0; i < nu; ++i) {
+    residual<T>(h, L, f, u, d.r.template as<T>());
+    asm_step<T>(h, L, d.r.template as<T>(), u);
+  }
+}
+
+template void vmult<double>(stmg_handle*, int, const double*, double*);
+template void vmult<float>(stmg_handle*, int, const float*, float*);
+template void smooth<double>(stmg_handle*, int, const double*, double*, int);
+template void smooth<float>(stmg_handle*, int, const float*, float*, int);
+template void vcycle<double>(stmg_handle*, int, const double*, double*);
+template void vcycle<float>(stmg_handle*, int, const float*, float*);
+template void prolongate<double>(stmg_handle*, int, const double*, double*, bool);
+template void prolongate<float>(stmg_handle*, int, const float*, float*, bool);
+template void restrict_<double>(stmg_handle*, int, const double*, double*);
+template void restrict_<float>(stmg_handle*, int, const float*, float*);
+
+// ------------------------------------------------------------------ relaxation estimate
+
+namespace {
+// eigenvalues of a small upper Hessenberg matrix by complex shifted QR (Wilkinson shifts)
+std::vector<std::complex<double>> hessenberg_eigs(const hm::Mat& H0) {
+  int n = H0.r;
+  using C = std::complex<double>;
+  std::vector<C> H((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = H0(i, j);
+  auto at = [&](int i, int j) -> C& { return H[(size_t)i * n + j]; };
+  std::vector<C> eig;
+  int hi = n - 1, iter = 0;
+  while (hi >= 0) {
+    if (hi == 0) { eig.push_back(at(0, 0)); break; }
+    int l = hi;
+    while (l > 0) {
+      double sc = std::abs(at(l, l)) + std::abs(at(l - 1, l - 1));
+      if (std::abs(at(l, l - 1)) <= 1e-15 * (sc > 0 ? sc : 1.0)) { at(l, l - 1) = 0; break; }
+      --l;
+    }
+    if (l == hi || ++iter > 500 * n) { eig.push_back(at(hi, hi)); --hi; iter = 0; continue; }
+    C a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+    C tr = a + d, det = a * d - b * c;
+    C disc = std::sqrt(tr * tr / 4.0 - det);
+    C e1 = tr / 2.0 + disc, e2 = tr / 2.0 - disc;
+    C mu = (std::abs(e1 - d) < std::abs(e2 - d)) ? e1 : e2;
+    // QR step on rows/cols l..hi of H - mu I with Givens rotations, then RQ + mu I
+    for (int i = l; i <= hi; ++i) at(i, i) -= mu;
+    std::vector<C> cs(hi - l), sn(hi - l);
+    for (int k = l; k < hi; ++k) {
+      C x = at(k, k), y = at(k + 1, k);
+      double r = std::sqrt(std::norm(x) + std::norm(y));
+      C cc = r > 0 ? x / r : C(1.0), ss = r > 0 ? y / r : C(0.0);
+      cs[k - l] = cc;
+      sn[k - l] = ss;
+      for (int j = k; j < n; ++j) {
+        C t1 = at(k, j), t2 = at(k + 1, j);
+        at(k, j) = std::conj(cc) * t1 + std::conj(ss) * t2;
+        at(k + 1, j) = -ss * t1 + cc * t2;
+      }
+    }
+    for (int k = l; k < hi; ++k) {
+      C cc = cs[k - l], ss = sn[k - l];
+      for (int i = 0; i <= std::min(k + 2, hi); ++i) {
+        C t1 = at(i, k), t2 = at(i, k + 1);
+        at(i, k) = t1 * cc + t2 * ss;
+        at(i, k + 1) = -t1 * std::conj(ss) + t2 * std::conj(cc);
+      }
+    }
+    for (int i = l; i <= hi; ++i) at(i, i) += mu;
+  }
+  return eig;
+}
+}  // namespace
+
+// omega_l = 2 / (lambda_max + lambda_min) of ASM * S (eq. relaxation), from the real parts of
+// the Ritz values of 15 Arnoldi steps with a deterministic start vector, clamped to (0, 1]
+void estimate_omegas(stmg_handle* h) {
+  hipStream_t s = h->stream;
+  const int steps = 15;
+  int n_t = h->tm.n_t;
+  DevBuf red(sizeof(double) * RED_BLOCKS * JC), dots(sizeof(double) * 64);
+  for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
+    Level& L = *h->levels[l];
+    long long n = L.nst(n_t);
+    DevBuf V(sizeof(double) * n * (steps + 1)), r(sizeof(double) * n), z(sizeof(double) * n);
+    DevBuf r32, z32;
+    if (!L.has64) { r32.alloc(sizeof(float) * n); z32.alloc(sizeof(float) * n); }
+    // start vector 1 + sin(0.7 g + 1.3 i + 0.1) / 2 on interior DoFs
+    std::vector<double> v0(n);
+    std::vector<unsigned char> mask = download<unsigned char>(L.mask.get(), L.g.nx, s);
+    for (int i = 0; i < n_t; ++i)
+      for (long long g = 0; g < L.g.nx; ++g)
+        v0[(size_t)i * L.g.nx + g] = mask[g] ? 1.0 + 0.5 * std::sin(0.7 * g + 1.3 * i + 0.1) : 0.0;
+    double nrm = 0.0;
+    for (double v : v0) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (double& v : v0) v /= nrm;
+    double* Vd = V.as<double>();
+    STMG_HIP(hipMemcpyAsync(Vd, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    hm::Mat H(steps + 1, steps);
+    double save = L.omega;
+    L.omega = 1.0;
+    int m = steps;
+    for (int j = 0; j < steps; ++j) {
+      vmult<double>(h, (int)l, Vd + j * n, r.as<double>());
+      if (L.has64) {
+        fill<double>(z.as<double>(), 0.0, n, s);
+        asm_step<double>(h, L, r.as<double>(), z.as<double>());
+      } else {
+        cast_d2f(r.as<double>(), r32.as<float>(), n, s);
+        fill<float>(z32.as<float>(), 0.0f, n, s);
+        asm_step<float>(h, L, r32.as<float>(), z32.as<float>());
+        cast_f2d(z32.as<float>(), z.as<double>(), n, s);
+      }
+      // classical Gram-Schmidt, twice
+      std::vector<double> hc(j + 2, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        multi_dot(Vd, n, j + 1, z.as<double>(), n, dots.as<double>(), red.as<double>(), s);
+        std::vector<double> hv = download<double>(dots.get(), j + 1, s);
+        multi_axpy_neg(Vd, n, j + 1, dots.as<double>(), z.as<double>(), n, s);
+        for (int i = 0; i <= j; ++i) hc[i] += hv[i];
+      }
+      multi_dot(z.as<double>(), n, 1, z.as<double>(), n, dots.as<double>(), red.as<double>(), s);
+      double nz = std::sqrt(download<double>(dots.get(), 1, s)[0]);
+      for (int i = 0; i <= j; ++i) H(i, j) = hc[i];
+      H(j + 1, j) = nz;
+      if (!(nz > 1e-12)) { m = j + 1; break; }
+      axpby<double>(1.0 / nz, z.as<double>(), 0.0, Vd + (j + 1) * n, n, s);
+    }
+    L.omega = save;
+    hm::Mat Hm(m, m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Hm(i, j) = H(i, j);
+    auto ev = hessenberg_eigs(Hm);
+    double lmax = -1e300, lmin = 1e300;
+    for (auto& e : ev) { lmax = std::max(lmax, e.real()); lmin = std::min(lmin, e.real()); }
+    double om = 2.0 / (lmax + lmin);
+    if (!std::isfinite(om)) om = 1.0;
+    L.omega = std::min(1.0, std::max(1e-3, om));
+  }
+}
+
+}  // namespace stmg

@@ -1,0 +1,44 @@
+// Host-side numerics of the set-up phase: 1D node sets, quadrature, Lagrange
+// bases, temporal matrices of dG(k)/cGP(k) and small dense linear algebra.
+#pragma once
+
+#include <vector>
+
+namespace stmg {
+namespace hm {
+
+using Vec = std::vector<double>;
+
+// Dense row-major matrix of small size.
+struct Mat {
+  int r = 0, c = 0;
+  Vec a;
+  Mat() = default;
+  Mat(int r_, int c_) : r(r_), c(c_), a((size_t)r_ * c_, 0.0) {}
+  double& operator()(int i, int j) { return a[(size_t)i * c + j]; }
+  double operator()(int i, int j) const { return a[(size_t)i * c + j]; }
+};
+
+Mat matmul(const Mat& A, const Mat& B);
+Mat inverse(const Mat& A);            // Gauss-Jordan with partial pivoting; throws if singular
+
+// n-point Gauss-Legendre rule on [0, 1].
+void gauss(int n, Vec& x, Vec& w);
+// n-point Gauss-Lobatto points on [0, 1] (n >= 2).
+Vec gauss_lobatto(int n);
+// n-point Gauss-Radau points on [0, 1] containing t = 1.
+Vec gauss_radau_right(int n);
+// Lagrange basis on `nodes`: val[q][i] = l_i(x_q), der[q][i] = l_i'(x_q).
+void lagrange(const Vec& nodes, const Vec& x, Mat& val, Mat& der);
+
+// Slab-level temporal data (Sections 3.1-3.2).
+struct Temporal {
+  int n_t = 0, nt_cell = 0, c = 0;
+  Mat M_T, A_T, N_T;      // n_t x n_t
+  Mat M_tau, N_tilde;     // diagonal blocks (ASM local temporal factors)
+};
+// problem: 0 heat, 1 wave; method: 0 dG, 1 cGP.
+Temporal temporal(int problem, int method, int k, int c, double tau);
+
+}  // namespace hm
+}  // namespace stmg

@@ -1,0 +1,86 @@
+// Host-callable launchers of the HIP kernels (all enqueue on the given stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "device.hpp"
+
+namespace stmg {
+
+// Host copy of the 1D tables of one spatial degree (row-major N x N).
+struct LevelTables {
+  int n = 0;
+  std::vector<double> S, D, gq, gw;
+};
+LevelTables make_level_tables(int p);
+
+// ---- operator (op_apply.hip) ----------------------------------------------------------
+// y += scale * S_interior x : interior rows only, Dirichlet columns ignored.
+template <class T>
+void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
+              T scale, hipStream_t s);
+
+// ---- vector kernels (blas.hip) --------------------------------------------------------------
+template <class T> void fill(T* y, T v, long long n, hipStream_t s);
+template <class T> void copy(const T* x, T* y, long long n, hipStream_t s);
+template <class T> void axpy(T a, const T* x, T* y, long long n, hipStream_t s);          // y += a x
+template <class T> void axpby(T a, const T* x, T b, T* y, long long n, hipStream_t s);    // y = a x + b y
+template <class T> void scal(T a, T* y, long long n, hipStream_t s);
+void cast_d2f(const double* x, float* y, long long n, hipStream_t s);
+void cast_f2d(const float* x, double* y, long long n, hipStream_t s);
+// On Dirichlet nodes (list bidx of length nb, per temporal plane of nx nodes, n_t planes):
+// y[b] = a * x[b] + c * y[b].
+template <class T>
+void boundary_axpby(const int* bidx, long long nb, long long nx, int n_t, T a, const T* x, T c, T* y,
+                    hipStream_t s);
+// Reduction workspace: RED_BLOCKS * JC doubles of device memory.
+constexpr int RED_BLOCKS = 1024;
+constexpr int JC = 8;
+// out[j] = sum_i V_j[i] * w[i] for j < k (V_j = V + j * ldv), double accumulation; out on device.
+void multi_dot(const double* V, long long ldv, int k, const double* w, long long n, double* out,
+               double* ws, hipStream_t s);
+// w -= sum_j h[j] V_j  (h on device)
+void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, double* w, long long n,
+                    hipStream_t s);
+// x += sum_j y[j] Z_j  (y on device, Z in T)
+template <class T>
+void multi_axpy_acc(const T* Z, long long ldz, int k, const double* y, double* x, long long n,
+                    hipStream_t s);
+// out[0] = sum x^2 (double accumulation), out[1] = 1 if a non-finite value was seen
+template <class T> void norm2_check(const T* x, long long n, double* out, double* ws, hipStream_t s);
+
+// ---- transfers (transfer.hip) ---------------------------------------------------------------
+// One 1D sweep along axis `ax` of a [n_t][n2][n1][n0] array (x fastest):
+// out[.., i, ..] (+)= sum_{k in row i} w[k] * in[.., col[k], ..] with CSR (ptr, col, w).
+// mask_in / mask_out: optional per-node interior flags (1 byte per node of the input /
+// output lattice): masked-out entries read as zero / are written as zero.
+template <class T>
+void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
+             const int* col, const T* w, const unsigned char* mask_in, const unsigned char* mask_out,
+             bool accumulate, hipStream_t s);
+
+// ---- smoother (asm.hip) ----------------------------------------------------------------------
+// Set-up: probe vectors (two planes) for colour `colour` (of 3^dim) and cell-local node b.
+void asm_probe_set(const GeomDesc& g, int colour, int b, double val, double* x, hipStream_t s);
+// Column b of A_KK (plane 0 of y) and M_KK (plane 1) for every cell of the colour;
+// blocks are column-major n_s x n_s per cell; Dirichlet nodes become identity rows/columns.
+void asm_extract(const GeomDesc& g, int colour, int b, const double* y, double* Ablk, double* Mblk,
+                 hipStream_t s);
+// Tinv[K][s] = (lam[K][s] M_tau + N~)^{-1} (nt x nt, row-major); *bad set if singular.
+template <class T>
+void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double* Mtau, const double* Nt,
+              T* Tinv, int* bad, hipStream_t s);
+template <class Tout> void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s);
+// u += omega * sum_K R_K^T (I (x) Q_K) Tinv_K (I (x) Q_K^T) R_K r on interior rows.
+template <class T>
+void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
+               T omega, hipStream_t s);
+
+// ---- coarse solve (coarse.hip) ---------------------------------------------------------------------
+// z[idx[i]] = sum_j Cinv[i][j] f[idx[j]] for the m interior DoFs of the coarsest level.
+template <class T>
+void coarse_apply(const T* Cinv, const long long* idx, int m, const T* f, T* z, hipStream_t s);
+
+}  // namespace stmg

@@ -1,0 +1,553 @@
+// Matrix-free space-time operator  y += scale * (M_T (x) A_h + N_T (x) M_h) x  on
+// interior rows (Section 4.1: S = sum_c P_c^T B_c^T D_c B_c P_c with sum
+// factorisation; the temporal factors are small dense matrices and A_h u^i,
+// M_h u^i are formed once per temporal DoF and reused).
+//
+// MI355X mapping.  One 64-lane wave per workgroup.  A "team" of p+1 lanes owns
+// one (spatial cell, output temporal DoF i) pair; lane t of the team holds the
+// z = t plane of the cell in registers ("XY layout": x and y sweeps are lane
+// local) or, after a transpose through LDS, the y = t plane ("XZ layout": x and
+// z sweeps are lane local).  The temporal mixing is done at the nodes while
+// gathering: a_i = sum_j (M_T)_ij x_j feeds the stiffness, b_i = sum_j (N_T)_ij x_j
+// the mass, so each team runs one fused  A_K a_i + M_K b_i  evaluation:
+//   values at Gauss points by S-sweeps, reference gradients by collocation
+//   D-sweeps on the Gauss points, geometry factors (per quadrature point,
+//   computed once per cell into LDS), and the transposed sweeps back.
+// Contributions are scatter-added with hardware FP atomics.  In 2D a team is a
+// single lane holding the whole cell.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace stmg {
+
+namespace {
+
+template <class T, int N>
+struct OpArgs {
+  Tables<T, N> tab;
+  GeomDesc g;
+  TemporalDev<T> tp;
+  const T* x;
+  T* y;
+  T scale;
+  int cpw;        // cells per workgroup
+  int nblocks;
+};
+
+// Geometry factor slots per quadrature point: 3D: G00 G01 G02 G11 G12 G22 dJw; 2D: G00 G01 G11 dJw.
+template <int DIM> constexpr int geo_slots() { return DIM == 3 ? 7 : 4; }
+
+// G = rho |det J| w J^{-1} J^{-T} and |det J| w at quadrature point (qx, qy, qz) of a cell.
+template <int DIM, int N>
+__device__ inline void geometry(const GeomDesc& g, const double (&gq)[N], const double (&gw)[N],
+                                long long cell, int cx, int cy, int cz, int qx, int qy, int qz,
+                                int q, double* out) {
+  double rho = g.rho ? (g.rho_q ? g.rho[cell * (long long)(DIM == 3 ? N * N * N : N * N) + q]
+                                : g.rho[cell])
+                     : 1.0;
+  double w = gw[qx] * gw[qy] * (DIM == 3 ? gw[qz] : 1.0);
+  if constexpr (DIM == 3) {
+    double J[3][3];
+    if (!g.verts) {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i][j] = (i == j) ? g.h[i] : 0.0;
+    } else {
+      double xi[3] = {gq[qx], gq[qy], gq[qz]};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i][j] = 0.0;
+      const long long sy = g.nc[0] + 1, sz = (long long)(g.nc[0] + 1) * (g.nc[1] + 1);
+      for (int v = 0; v < 8; ++v) {
+        int b0 = v & 1, b1 = (v >> 1) & 1, b2 = (v >> 2) & 1;
+        const double* X = g.verts + 3 * ((cz + b2) * sz + (cy + b1) * sy + (cx + b0));
+        double n0 = b0 ? xi[0] : 1.0 - xi[0], n1 = b1 ? xi[1] : 1.0 - xi[1],
+               n2 = b2 ? xi[2] : 1.0 - xi[2];
+        double d0 = (b0 ? 1.0 : -1.0) * n1 * n2, d1 = n0 * (b1 ? 1.0 : -1.0) * n2,
+               d2 = n0 * n1 * (b2 ? 1.0 : -1.0);
+        for (int i = 0; i < 3; ++i) {
+          J[i][0] += X[i] * d0;
+          J[i][1] += X[i] * d1;
+          J[i][2] += X[i] * d2;
+        }
+      }
+    }
+    double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    double id = 1.0 / det;
+    // inverse: Jinv[i][j] = cof(J)[j][i] / det
+    double Ji[3][3];
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    double s = fabs(det) * w;
+    double f = rho * s;
+    auto K = [&](int a, int b) { return Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2]; };
+    out[0] = f * K(0, 0);
+    out[1] = f * K(0, 1);
+    out[2] = f * K(0, 2);
+    out[3] = f * K(1, 1);
+    out[4] = f * K(1, 2);
+    out[5] = f * K(2, 2);
+    out[6] = s;
+  } else {
+    double J[2][2];
+    if (!g.verts) {
+      J[0][0] = g.h[0]; J[0][1] = 0.0; J[1][0] = 0.0; J[1][1] = g.h[1];
+    } else {
+      double xi[2] = {gq[qx], gq[qy]};
+      J[0][0] = J[0][1] = J[1][0] = J[1][1] = 0.0;
+      const long long sy = g.nc[0] + 1;
+      for (int v = 0; v < 4; ++v) {
+        int b0 = v & 1, b1 = (v >> 1) & 1;
+        const double* X = g.verts + 2 * ((cy + b1) * sy + (cx + b0));
+        double n0 = b0 ? xi[0] : 1.0 - xi[0], n1 = b1 ? xi[1] : 1.0 - xi[1];
+        double d0 = (b0 ? 1.0 : -1.0) * n1, d1 = n0 * (b1 ? 1.0 : -1.0);
+        for (int i = 0; i < 2; ++i) { J[i][0] += X[i] * d0; J[i][1] += X[i] * d1; }
+      }
+    }
+    double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    double id = 1.0 / det;
+    double Ji[2][2] = {{J[1][1] * id, -J[0][1] * id}, {-J[1][0] * id, J[0][0] * id}};
+    double s = fabs(det) * w;
+    double f = rho * s;
+    out[0] = f * (Ji[0][0] * Ji[0][0] + Ji[0][1] * Ji[0][1]);
+    out[1] = f * (Ji[0][0] * Ji[1][0] + Ji[0][1] * Ji[1][1]);
+    out[2] = f * (Ji[1][0] * Ji[1][0] + Ji[1][1] * Ji[1][1]);
+    out[3] = s;
+  }
+}
+
+// ---- register-array sweeps on an N x N plane  A[r][c] ------------------------------
+// out[r][q] = sum_c M[q][c] in[r][c]      (contract the column index)
+template <class T, int N>
+__device__ inline void cols(const T (&M)[N][N], const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) s += M[q][c] * in[r][c];
+      out[r][q] = s;
+    }
+}
+// out[r][c] = sum_q M[q][c] in[r][q]      (transposed, column index)
+template <class T, int N>
+__device__ inline void cols_t(const T (&M)[N][N], const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) s += M[q][c] * in[r][q];
+      out[r][c] = s;
+    }
+}
+// out[q][c] = sum_r M[q][r] in[r][c]      (contract the row index)
+template <class T, int N>
+__device__ inline void rows(const T (&M)[N][N], const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int r = 0; r < N; ++r) s += M[q][r] * in[r][c];
+      out[q][c] = s;
+    }
+}
+// out[r][c] = sum_q M[q][r] in[q][c]      (transposed, row index)
+template <class T, int N>
+__device__ inline void rows_t(const T (&M)[N][N], const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) s += M[q][r] * in[q][c];
+      out[r][c] = s;
+    }
+}
+
+// XY (lane t = z, A[y][x]) <-> XZ (lane t = y, A[z][x]) transpose inside one team.
+template <class T, int N>
+__device__ inline void xy_to_xz(T* scr, int t, const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int y = 0; y < N; ++y)
+#pragma unroll
+    for (int x = 0; x < N; ++x) scr[(t * N + y) * N + x] = in[y][x];
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x) out[z][x] = scr[(z * N + t) * N + x];
+  __syncthreads();
+}
+template <class T, int N>
+__device__ inline void xz_to_xy(T* scr, int t, const T (&in)[N][N], T (&out)[N][N]) {
+#pragma unroll
+  for (int z = 0; z < N; ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x) scr[(z * N + t) * N + x] = in[z][x];
+  __syncthreads();
+#pragma unroll
+  for (int y = 0; y < N; ++y)
+#pragma unroll
+    for (int x = 0; x < N; ++x) out[y][x] = scr[(t * N + y) * N + x];
+  __syncthreads();
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(64) void st_apply3(OpArgs<T, N> A) {
+  constexpr int NQ = N * N * N;
+  constexpr int TPW = 64 / N;
+  constexpr int GS = 7;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* geo = reinterpret_cast<T*>(smem_raw);                  // [cpw][NQ][GS]
+  T* scr_all = geo + (size_t)A.cpw * NQ * GS;               // [TPW + 1][NQ] (last: idle lanes)
+  const GeomDesc& g = A.g;
+  const int p = N - 1;
+  const int lane = threadIdx.x;
+  const int team = lane / N;
+  const int t = lane - team * N;
+  const bool lane_ok = team < TPW;
+  T* scr = scr_all + (size_t)(lane_ok ? team : TPW) * NQ;
+
+  const int blk = xcd_swizzle(blockIdx.x, A.nblocks);
+  const long long cell0 = (long long)blk * A.cpw;
+
+  // geometry factors of this block's cells
+  for (int idx = lane; idx < A.cpw * NQ; idx += 64) {
+    int lc = idx / NQ, q = idx - lc * NQ;
+    long long cell = cell0 + lc;
+    if (cell >= g.ncells) continue;
+    int cx = (int)(cell % g.nc[0]);
+    int cy = (int)((cell / g.nc[0]) % g.nc[1]);
+    int cz = (int)(cell / ((long long)g.nc[0] * g.nc[1]));
+    int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+    double o[7];
+    geometry<3, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, cz, qx, qy, qz, q, o);
+    T* dst = geo + ((size_t)lc * NQ + q) * GS;
+#pragma unroll
+    for (int s = 0; s < GS; ++s) dst[s] = (T)o[s];
+  }
+  __syncthreads();
+
+  const int n_t = A.tp.n_t;
+  const int items = A.cpw * n_t;
+  const long long plane = g.nx;
+  for (int it0 = 0; it0 < items; it0 += TPW) {
+    const int item = it0 + team;
+    const int lc = item / n_t;
+    const int i = item - lc * n_t;
+    const long long cell = cell0 + lc;
+    const bool act = lane_ok && item < items && cell < g.ncells;
+    int cx = 0, cy = 0, cz = 0;
+    if (act) {
+      cx = (int)(cell % g.nc[0]);
+      cy = (int)((cell / g.nc[0]) % g.nc[1]);
+      cz = (int)(cell / ((long long)g.nc[0] * g.nc[1]));
+    }
+    // node offsets and interior mask of this lane's z-plane
+    const int gz = cz * p + t;
+    const bool zb = (gz == 0) || (gz == g.nn[2] - 1);
+    long long base = ((long long)gz * g.nn[1] + (long long)cy * p) * g.nn[0] + (long long)cx * p;
+    bool inner[N][N];
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x) {
+        int gy = cy * p + y, gx = cx * p + x;
+        inner[y][x] = act && !zb && gy != 0 && gy != g.nn[1] - 1 && gx != 0 && gx != g.nn[0] - 1;
+      }
+
+    // gather with temporal mixing: a = (M_T x)_i (stiffness input), b = (N_T x)_i (mass input)
+    T a[N][N], b[N][N];
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x) { a[y][x] = 0; b[y][x] = 0; }
+    if (act) {
+      for (int k = A.tp.mptr[i]; k < A.tp.mptr[i + 1]; ++k) {
+        const T c = A.tp.mval[k];
+        const T* xj = A.x + (long long)A.tp.mcol[k] * plane + base;
+#pragma unroll
+        for (int y = 0; y < N; ++y)
+#pragma unroll
+          for (int x = 0; x < N; ++x)
+            if (inner[y][x]) a[y][x] += c * xj[(long long)y * g.nn[0] + x];
+      }
+      for (int k = A.tp.nptr[i]; k < A.tp.nptr[i + 1]; ++k) {
+        const T c = A.tp.nval[k];
+        const T* xj = A.x + (long long)A.tp.ncol[k] * plane + base;
+#pragma unroll
+        for (int y = 0; y < N; ++y)
+#pragma unroll
+          for (int x = 0; x < N; ++x)
+            if (inner[y][x]) b[y][x] += c * xj[(long long)y * g.nn[0] + x];
+      }
+    }
+
+    const auto& S = A.tab.S;
+    const auto& D = A.tab.D;
+    T t0[N][N], t1[N][N], t2[N][N];
+
+    // mass path: b -> values at Gauss points (x, y in XY layout, z after transpose)
+    cols<T, N>(S, b, t0);                 // [y][qx]
+    rows<T, N>(S, t0, b);                 // [qy][qx]
+    xy_to_xz<T, N>(scr, t, b, t0);        // lane = qy : [z][qx]
+    T u[N][N];
+    rows<T, N>(S, t0, u);                 // [qz][qx] values of b
+    // u <- m = |det J| w * b_hat
+    const T* gcell = geo + (size_t)(act ? lc : 0) * NQ * GS;
+#pragma unroll
+    for (int qz = 0; qz < N; ++qz)
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) u[qz][qx] *= gcell[((qz * N + t) * N + qx) * GS + 6];
+
+    // stiffness path: a -> values and y-derivative at Gauss points (XY), then XZ
+    cols<T, N>(S, a, t0);                 // [y][qx]
+    rows<T, N>(S, t0, t1);                // [qy][qx] values
+    rows<T, N>(D, t1, t2);                // [qy][qx] d/dy
+    xy_to_xz<T, N>(scr, t, t1, t0);       // values  [z][qx]
+    xy_to_xz<T, N>(scr, t, t2, t1);       // dy      [z][qx]
+    rows<T, N>(S, t0, a);                 // a  = values at (qx, qy=t, qz)
+    rows<T, N>(S, t1, b);                 // b  = d/dy at Gauss points (reuse register set)
+
+    // quadrature-point operation; accumulate the x/z-derivative transposes into u
+#pragma unroll
+    for (int qz = 0; qz < N; ++qz)
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) {
+        T dx = 0, dz = 0;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          dx += D[qx][r] * a[qz][r];
+          dz += D[qz][r] * a[r][qx];
+        }
+        const T dy = b[qz][qx];
+        const T* G = gcell + ((qz * N + t) * N + qx) * GS;
+        const T gx = G[0] * dx + G[1] * dy + G[2] * dz;
+        const T gy = G[1] * dx + G[3] * dy + G[4] * dz;
+        const T gz = G[2] * dx + G[4] * dy + G[5] * dz;
+        t2[qz][qx] = gy;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          u[qz][r] += D[qx][r] * gx;
+          u[r][qx] += D[qz][r] * gz;
+        }
+      }
+    // integrate in z (XZ layout), then back to XY for y and x
+    rows_t<T, N>(S, u, t0);               // [z][qx]
+    rows_t<T, N>(S, t2, t1);              // gy integrated in z: [z][qx]
+    xz_to_xy<T, N>(scr, t, t0, u);        // lane = z: [qy][qx]
+    xz_to_xy<T, N>(scr, t, t1, t2);       // [qy][qx]
+    rows_t<T, N>(D, t2, t0);              // d/dy transpose
+#pragma unroll
+    for (int qy = 0; qy < N; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) u[qy][qx] += t0[qy][qx];
+    rows_t<T, N>(S, u, t1);               // [y][qx]
+    cols_t<T, N>(S, t1, t2);              // [y][x]
+
+    if (act) {
+      T* yi = A.y + (long long)i * plane + base;
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+          if (inner[y][x]) atomic_add(yi + (long long)y * g.nn[0] + x, A.scale * t2[y][x]);
+    }
+  }
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A) {
+  constexpr int NQ = N * N;
+  constexpr int GS = 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* geo = reinterpret_cast<T*>(smem_raw);                  // [cpw][NQ][GS]
+  const GeomDesc& g = A.g;
+  const int p = N - 1;
+  const int lane = threadIdx.x;
+  const int blk = xcd_swizzle(blockIdx.x, A.nblocks);
+  const long long cell0 = (long long)blk * A.cpw;
+  for (int idx = lane; idx < A.cpw * NQ; idx += 64) {
+    int lc = idx / NQ, q = idx - lc * NQ;
+    long long cell = cell0 + lc;
+    if (cell >= g.ncells) continue;
+    int cx = (int)(cell % g.nc[0]), cy = (int)(cell / g.nc[0]);
+    double o[7];
+    geometry<2, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, 0, q % N, q / N, 0, q, o);
+    T* dst = geo + ((size_t)lc * NQ + q) * GS;
+#pragma unroll
+    for (int s = 0; s < GS; ++s) dst[s] = (T)o[s];
+  }
+  __syncthreads();
+  const int n_t = A.tp.n_t;
+  const int items = A.cpw * n_t;
+  const long long plane = g.nx;
+  for (int it0 = 0; it0 < items; it0 += 64) {
+    const int item = it0 + lane;
+    const int lc = item / n_t;
+    const int i = item - lc * n_t;
+    const long long cell = cell0 + lc;
+    if (item >= items || cell >= g.ncells) continue;
+    const int cx = (int)(cell % g.nc[0]), cy = (int)(cell / g.nc[0]);
+    long long base = (long long)cy * p * g.nn[0] + (long long)cx * p;
+    bool inner[N][N];
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x) {
+        int gy = cy * p + y, gx = cx * p + x;
+        inner[y][x] = gy != 0 && gy != g.nn[1] - 1 && gx != 0 && gx != g.nn[0] - 1;
+      }
+    T a[N][N], b[N][N];
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x) { a[y][x] = 0; b[y][x] = 0; }
+    for (int k = A.tp.mptr[i]; k < A.tp.mptr[i + 1]; ++k) {
+      const T c = A.tp.mval[k];
+      const T* xj = A.x + (long long)A.tp.mcol[k] * plane + base;
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+          if (inner[y][x]) a[y][x] += c * xj[(long long)y * g.nn[0] + x];
+    }
+    for (int k = A.tp.nptr[i]; k < A.tp.nptr[i + 1]; ++k) {
+      const T c = A.tp.nval[k];
+      const T* xj = A.x + (long long)A.tp.ncol[k] * plane + base;
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x)
+          if (inner[y][x]) b[y][x] += c * xj[(long long)y * g.nn[0] + x];
+    }
+    const auto& S = A.tab.S;
+    const auto& D = A.tab.D;
+    T t0[N][N], ah[N][N], bh[N][N], gx[N][N], gy[N][N];
+    cols<T, N>(S, a, t0);
+    rows<T, N>(S, t0, ah);      // [qy][qx]
+    cols<T, N>(S, b, t0);
+    rows<T, N>(S, t0, bh);
+    const T* gcell = geo + (size_t)lc * NQ * GS;
+#pragma unroll
+    for (int qy = 0; qy < N; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) {
+        T dx = 0, dy = 0;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          dx += D[qx][r] * ah[qy][r];
+          dy += D[qy][r] * ah[r][qx];
+        }
+        const T* G = gcell + (qy * N + qx) * GS;
+        gx[qy][qx] = G[0] * dx + G[1] * dy;
+        gy[qy][qx] = G[1] * dx + G[2] * dy;
+        bh[qy][qx] *= G[3];
+      }
+    cols_t<T, N>(D, gx, t0);
+    rows_t<T, N>(D, gy, ah);
+#pragma unroll
+    for (int qy = 0; qy < N; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < N; ++qx) bh[qy][qx] += t0[qy][qx] + ah[qy][qx];
+    rows_t<T, N>(S, bh, t0);    // [y][qx]
+    cols_t<T, N>(S, t0, ah);    // [y][x]
+    T* yi = A.y + (long long)i * plane + base;
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x)
+        if (inner[y][x]) atomic_add(yi + (long long)y * g.nn[0] + x, A.scale * ah[y][x]);
+  }
+}
+
+template <class T, int N>
+Tables<T, N> make_tables(const LevelTables& lt) {
+  Tables<T, N> tb;
+  for (int q = 0; q < N; ++q) {
+    tb.gq[q] = lt.gq[q];
+    tb.gw[q] = lt.gw[q];
+    for (int i = 0; i < N; ++i) {
+      tb.S[q][i] = (T)lt.S[q * N + i];
+      tb.D[q][i] = (T)lt.D[q * N + i];
+    }
+  }
+  return tb;
+}
+
+// cells per workgroup: fill the teams of one wave as evenly as possible
+int pick_cpw(int teams, int n_t) {
+  int best = 1;
+  double be = -1.0;
+  for (int c = 1; c <= 16; ++c) {
+    int items = c * n_t;
+    int rounds = (items + teams - 1) / teams;
+    double eff = (double)items / (rounds * teams);
+    if (eff > be + 1e-9) { be = eff; best = c; }
+    if (items >= 4 * teams) break;
+  }
+  return best;
+}
+
+template <class T, int N>
+void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp,
+                  const T* x, T* y, T scale, hipStream_t s) {
+  OpArgs<T, N> A;
+  A.tab = make_tables<T, N>(lt);
+  A.g = g;
+  A.tp = tp;
+  A.x = x;
+  A.y = y;
+  A.scale = scale;
+  if (g.dim == 3) {
+    constexpr int NQ = N * N * N;
+    int teams = 64 / N;
+    A.cpw = pick_cpw(teams, tp.n_t);
+    A.nblocks = ceil_div(g.ncells, A.cpw);
+    size_t lds = sizeof(T) * ((size_t)A.cpw * NQ * 7 + (size_t)(teams + 1) * NQ);
+    hipLaunchKernelGGL((st_apply3<T, N>), dim3(A.nblocks), dim3(64), lds, s, A);
+  } else {
+    constexpr int NQ = N * N;
+    A.cpw = pick_cpw(64, tp.n_t);
+    A.nblocks = ceil_div(g.ncells, A.cpw);
+    size_t lds = sizeof(T) * ((size_t)A.cpw * NQ * 4);
+    hipLaunchKernelGGL((st_apply2<T, N>), dim3(A.nblocks), dim3(64), lds, s, A);
+  }
+  STMG_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+template <class T>
+void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
+              T scale, hipStream_t s) {
+  if (g.ncells == 0 || tp.n_t == 0) return;
+  switch (g.n) {
+    case 2: launch_apply<T, 2>(g, lt, tp, x, y, scale, s); break;
+    case 3: launch_apply<T, 3>(g, lt, tp, x, y, scale, s); break;
+    case 4: launch_apply<T, 4>(g, lt, tp, x, y, scale, s); break;
+    case 5: launch_apply<T, 5>(g, lt, tp, x, y, scale, s); break;
+    default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
+  }
+}
+
+template void st_apply<double>(const GeomDesc&, const LevelTables&, const TemporalDev<double>&,
+                               const double*, double*, double, hipStream_t);
+template void st_apply<float>(const GeomDesc&, const LevelTables&, const TemporalDev<float>&,
+                              const float*, float*, float, hipStream_t);
+
+}  // namespace stmg

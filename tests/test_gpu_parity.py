@@ -1,0 +1,166 @@
+"""GPU parity: the C-ABI library against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances: FP64 kernels accumulate with hardware atomics (summation order is not
+fixed), so results agree to a few ulps of the largest entry: 1e-12 relative to the
+max norm.  FP32 kernels: 2e-5 (a few FP32 ulps times the sum-factorisation depth).
+Solutions: 1e-10 relative (FP64 path), true residual 1e-8 (FP32-preconditioned path).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import stmg_inputs as si
+from oracle import krylov, mg, spacetime
+from tests.gpu_common import CASES, oracle_op, problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _handle(cfg, verts, coef, **kw):
+    from paper_2408_04372_amd import Handle
+    kw.setdefault("vcycle_dtypes", 3)
+    return Handle(cfg, verts, coef, **kw)
+
+
+def _t(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype).contiguous()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vmult_fp64_fp32(name):
+    cfg, verts, coef = problem(name)
+    print(f"case {name}", flush=True)
+    op = oracle_op(cfg, verts, coef)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((cfg.n_t, cfg.n_x))
+    ref = op.apply(x)
+    with _handle(cfg, verts, coef, omega=0.5) as h:
+        y = torch.empty(cfg.n_t * cfg.n_x, dtype=torch.float64, device=DEV)
+        h.vmult(_t(x).view(-1), y)
+        assert rel_err(_np(y), ref) < 1e-12
+        y32 = torch.empty(cfg.n_t * cfg.n_x, dtype=torch.float32, device=DEV)
+        h.vmult(_t(x, torch.float32).view(-1), y32)
+        assert rel_err(_np(y32), ref) < 2e-5
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2",
+                                  "heat2d_q4_cgp2_pert", "wave3d_q2_cgp1_ragged"])
+def test_transfers_and_coarse_operators(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op, omegas=[1.0] * 16)
+    L = len(H.levels)
+    rng = np.random.default_rng(4)
+    with _handle(cfg, verts, coef, omega=0.5) as h:
+        assert h.info["n_levels"] == L
+        for l in range(L):
+            lev = H.levels[L - 1 - l]
+            assert h.info["n_x"][l] == lev.op.n_x and h.info["p"][l] == lev.op.space.p
+            x = rng.standard_normal(lev.S.shape[0])
+            y = torch.empty(x.size, dtype=torch.float64, device=DEV)
+            h.vmult(_t(x), y, level=l)
+            assert rel_err(_np(y), lev.S @ x) < 1e-12
+        for l in range(L - 1):
+            io = L - 1 - l          # oracle index of the fine level
+            nc = H.levels[io - 1].S.shape[0]
+            nf = H.levels[io].S.shape[0]
+            xc = rng.standard_normal(nc)
+            xf = rng.standard_normal(nf)
+            for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+                f = torch.empty(nf, dtype=dt, device=DEV)
+                h.prolongate(_t(xc, dt), f, level=l)
+                assert rel_err(_np(f), H.prolong(io, xc)) < tol
+                c = torch.empty(nc, dtype=dt, device=DEV)
+                h.restrict(_t(xf, dt), c, level=l)
+                assert rel_err(_np(c), H.restrict(io, xf)) < tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_smoother(name):
+    cfg, verts, coef = problem(name)
+    print(f"case {name}", flush=True)
+    op = oracle_op(cfg, verts, coef)
+    lev = mg.Level(op=op, S=op.matrix())
+    lev.blocks = mg.asm_blocks(op, lev.S)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(lev.S.shape[0])
+    x0 = rng.standard_normal(lev.S.shape[0])
+    omega = 0.37
+    ref = mg.smooth(lev, b, x0, 2, omega=omega)
+    with _handle(cfg, verts, coef, omega=omega) as h:
+        for dt, tol in ((torch.float64, 1e-11), (torch.float32, 2e-4)):
+            x = _t(x0, dt)
+            h.smooth(_t(b, dt), x, steps=2, level=0)
+            assert rel_err(_np(x), ref) < tol, dt
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2",
+                                  "wave2d_q3_dg2", "heat3d_q1_dg0"])
+def test_vcycle(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op, n_smooth=cfg.n_smooth)
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(op.matrix().shape[0])
+    ref = H.vcycle(r)
+    with _handle(cfg, verts, coef, omega=0.5) as h:
+        L = h.info["n_levels"]
+        for l in range(L - 1):
+            h.set_omega(l, H.levels[L - 1 - l].omega)
+        for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+            z = torch.empty(r.size, dtype=dt, device=DEV)
+            h.vcycle(_t(r, dt), z)
+            assert rel_err(_np(z), ref) < tol, dt
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2"])
+def test_omega_estimate(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op)
+    with _handle(cfg, verts, coef, omega=0.0) as h:
+        L = h.info["n_levels"]
+        got = h.info["omega"][: L - 1]
+        ref = [H.levels[L - 1 - l].omega for l in range(L - 1)]
+    assert np.allclose(got, ref, rtol=1e-6)
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2",
+                                  "heat2d_q4_cgp2_pert", "wave3d_q2_cgp1_ragged"])
+def test_solve_fp64_matches_direct(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    b = si.random_slab_vector(cfg, 11)
+    xd = op.solve(b)
+    with _handle(cfg, verts, coef, rtol=1e-12, precision=0, max_iter=300) as h:
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        info = h.solve(_t(b).view(-1), x)
+        err = np.linalg.norm(_np(x) - xd.ravel()) / np.linalg.norm(xd)
+    print(name, info)
+    assert info["rel_residual"] <= 1e-12
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2"])
+def test_solve_fp32_preconditioner(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    b = si.random_slab_vector(cfg, 12)
+    xd = op.solve(b)
+    with _handle(cfg, verts, coef, rtol=1e-8, precision=1, max_iter=300) as h:
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        info = h.solve(_t(b).view(-1), x)
+        xs = _np(x)
+    res = np.linalg.norm(b.ravel() - op.matrix() @ xs) / np.linalg.norm(b)
+    err = np.linalg.norm(xs - xd.ravel()) / np.linalg.norm(xd)
+    print(name, info, "oracle residual", res, "error", err)
+    assert res <= 1e-8
+    assert info["rel_residual"] <= 1e-8
