@@ -81,7 +81,10 @@ typedef struct {
   int32_t min_p;           /* p-coarsening stops at this degree (>= 1) */
   int32_t coarse_cells;    /* h-coarsening stops before a level has fewer cells per direction */
   int32_t vcycle_dtypes;   /* bit 0: build FP64 V-cycle data, bit 1: FP32; 0 = from precision */
-  double omega;            /* > 0: relaxation used on every level; <= 0: estimate per level (eq. relaxation) */
+  double omega;            /* > 0: relaxation used on every level; == 0: per level from eq. relaxation,
+                              omega_l = 2 / (lambda_max + lambda_min) of ASM * S_l (Arnoldi estimate);
+                              < 0: per level omega_l = |omega| / lambda_max (damps the top of the
+                              spectrum; the paper's rule leaves it undamped for high p) */
   int32_t precision;       /* stmg_precision: preconditioner used by stmg_solve */
   int32_t restart;         /* FGMRES restart length m >= 1 */
   int32_t max_iter;        /* total FGMRES iterations allowed */
@@ -164,6 +167,23 @@ stmg_status stmg_restrict(stmg_handle* h, int level, int dtype, const void* fine
  * not reached within max_iter, STMG_E_NONFINITE for NaN/Inf.  Synchronous.
  * info may be NULL. */
 stmg_status stmg_solve(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
+
+/* Event-timed totals of the finest-level kernels, accumulated over stmg_solve calls:
+ * the matrix-free operator (every finest-level operator launch: outer products,
+ * residuals inside the V-cycle) and the smoother apply kernel. */
+typedef struct {
+  int64_t n_operator;       /* finest-level operator kernel launches */
+  int64_t n_smoother;       /* finest-level smoother kernel launches */
+  double t_operator;        /* summed kernel durations, seconds (hipEvents on the handle's stream) */
+  double t_smoother;
+} stmg_kernel_stats;
+
+/* Copy the accumulated finest-level kernel statistics; reset != 0 clears them afterwards. */
+stmg_status stmg_kernel_stats_get(stmg_handle* h, stmg_kernel_stats* out, int reset);
+
+/* Select the preconditioner used by stmg_solve (stmg_precision); the matching
+ * V-cycle data must have been built (vcycle_dtypes). */
+stmg_status stmg_set_precision(stmg_handle* h, int precision);
 
 /* Override the relaxation parameter of one level (omega > 0). */
 stmg_status stmg_set_omega(stmg_handle* h, int level, double omega);

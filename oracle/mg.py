@@ -15,7 +15,8 @@ Section 4 of the paper.  Readings where the paper is silent:
     Dirichlet DoF is its own 1x1 identity block.  One step is
     u <- u + omega * sum_T R_T^T S_TT^{-1} R_T (f - S u).
   * omega (eq. relaxation): 2 / (lambda_max + lambda_min) from real parts of the
-    Ritz values of 15 Arnoldi steps on ASM * S, clamped to (0, 1].
+    Ritz values of 15 Arnoldi steps on ASM * S, clamped to (0, 1].  Optional
+    alternative (omega_rule < 0): |omega_rule| / lambda_max.
   * coarsest level: exact sparse LU.  V-cycle: Alg. stmg with nu1 = nu2 = n_smooth
     and zero initial guesses.
 """
@@ -179,8 +180,13 @@ def arnoldi_start(n_t: int, bmask: np.ndarray) -> np.ndarray:
     return v.ravel()
 
 
-def estimate_omega(level: Level, steps: int = 15) -> float:
-    """omega = 2/(lambda_max + lambda_min) from Arnoldi Ritz values of ASM * S."""
+def estimate_omega(level: Level, steps: int = 15, rule: float = 0.0) -> float:
+    """omega = 2/(lambda_max + lambda_min) from Arnoldi Ritz values of ASM * S (eq. relaxation).
+
+    rule < 0 selects |rule| / lambda_max instead: the paper's rule balances the extreme
+    eigenvalues, which for high p leaves the top of the spectrum almost undamped
+    (factor close to -1); scaling by the largest Ritz value damps it.
+    """
     v = arnoldi_start(level.op.n_t, level.op.bmask)
     n = len(v)
     V = np.zeros((steps + 1, n))
@@ -198,7 +204,7 @@ def estimate_omega(level: Level, steps: int = 15) -> float:
             break
         V[j + 1] = w / H[j + 1, j]
     ev = np.linalg.eigvals(H[:m, :m]).real
-    om = 2.0 / (ev.max() + ev.min())
+    om = -rule / ev.max() if rule < 0 else 2.0 / (ev.max() + ev.min())
     return float(min(max(om, 1e-3), 1.0))
 
 
@@ -208,7 +214,7 @@ class Hierarchy:
     """Levels ordered coarsest (index 0) to finest (index L), as in Alg. stmg."""
 
     def __init__(self, fine_op: spacetime.SlabOperator, min_p: int = 1, coarse_cells: int = 2,
-                 omegas: Optional[List[float]] = None, n_smooth: int = 1):
+                 omegas: Optional[List[float]] = None, n_smooth: int = 1, omega_rule: float = 0.0):
         spaces = level_spaces(fine_op.space, min_p, coarse_cells)[::-1]
         self.n_smooth = n_smooth
         self.levels: List[Level] = []
@@ -227,7 +233,7 @@ class Hierarchy:
             if omegas is not None:
                 lev.omega = omegas[i]
             else:
-                lev.omega = estimate_omega(lev)
+                lev.omega = estimate_omega(lev, rule=omega_rule)
 
     @property
     def omegas(self):

@@ -66,6 +66,14 @@ class Info(ctypes.Structure):
     ]
 
 
+class KernelStats(ctypes.Structure):
+    _fields_ = [("n_operator", ctypes.c_int64), ("n_smoother", ctypes.c_int64),
+                ("t_operator", ctypes.c_double), ("t_smoother", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _LIB = None
 
 # exported symbols and their argument types
@@ -83,6 +91,8 @@ _SIGS = {
     "stmg_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SolveInfo)],
                    ctypes.c_int),
     "stmg_set_omega": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+    "stmg_set_precision": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "stmg_kernel_stats_get": ([ctypes.c_void_p, ctypes.POINTER(KernelStats), ctypes.c_int], ctypes.c_int),
     "stmg_query": ([ctypes.c_void_p, ctypes.POINTER(Info)], ctypes.c_int),
     "stmg_destroy": ([ctypes.c_void_p], None),
     "stmg_last_error": ([], ctypes.c_char_p),
@@ -237,6 +247,14 @@ class Handle:
         if code != 0 and (raise_on_noconv or code != 4):
             _check(code)
         return out
+
+    def set_precision(self, precision: int):
+        _check(self.lib.stmg_set_precision(self.h, int(precision)))
+
+    def kernel_stats(self, reset: bool = False) -> dict:
+        ks = KernelStats()
+        _check(self.lib.stmg_kernel_stats_get(self.h, ctypes.byref(ks), 1 if reset else 0))
+        return ks.as_dict()
 
     def set_omega(self, level: int, omega: float):
         _check(self.lib.stmg_set_omega(self.h, level, float(omega)))

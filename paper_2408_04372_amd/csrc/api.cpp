@@ -213,6 +213,36 @@ stmg_status stmg_solve(stmg_handle* h, const double* b, double* x, stmg_solve_in
   });
 }
 
+stmg_status stmg_kernel_stats_get(stmg_handle* h, stmg_kernel_stats* out, int reset) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!out) stmg::fail(STMG_E_ARG, "out is NULL");
+    h->ktimer.flush();
+    out->n_operator = h->ktimer.n[0];
+    out->n_smoother = h->ktimer.n[1];
+    out->t_operator = h->ktimer.t[0];
+    out->t_smoother = h->ktimer.t[1];
+    if (reset) {
+      h->ktimer.n[0] = h->ktimer.n[1] = 0;
+      h->ktimer.t[0] = h->ktimer.t[1] = 0.0;
+    }
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_set_precision(stmg_handle* h, int precision) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (precision < 0 || precision > 2) stmg::fail(STMG_E_ARG, "precision must be 0, 1 or 2");
+    check_dtype(h, precision == STMG_PREC_FP64 ? STMG_F64 : STMG_F32, true, 0);
+    if (precision != h->cfg.precision) {
+      h->cfg.precision = precision;
+      h->krylov_m = 0;      // workspace layout depends on the precision
+    }
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_set_omega(stmg_handle* h, int level, double omega) {
   return guarded([&]() -> stmg_status {
     stmg::Level& L = level_of(h, level);

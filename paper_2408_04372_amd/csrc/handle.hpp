@@ -65,6 +65,20 @@ struct Timer {               // event-based bucket timer for stmg_solve
 };
 enum { TB_SMOOTH = 0, TB_GMG = 1, TB_OP = 2, TB_OTHER = 3 };
 
+// event pairs around individual finest-level kernel launches (operator / smoother)
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;   // 2 per record
+  std::vector<int> kind;
+  size_t used = 0;
+  bool on = false;
+  int64_t n[2] = {0, 0};
+  double t[2] = {0.0, 0.0};
+  void begin(int k, hipStream_t s);
+  void end(hipStream_t s);
+  void flush();                 // synchronises on the last event and accumulates
+  ~KernelTimer();
+};
+
 struct CnnState;              // learned stage (cnn.hip)
 void cnn_free(CnnState* c);
 
@@ -83,6 +97,7 @@ struct stmg_handle {
   stmg::DevBuf V, Z64, Z32, w, tmp32a, tmp32b, dots, red, hbuf;
   int krylov_m = 0;
   stmg::Timer timer;
+  stmg::KernelTimer ktimer;
   double setup_seconds = 0.0;
   int64_t bytes_at_create = 0;
   stmg::CnnState* cnn = nullptr;

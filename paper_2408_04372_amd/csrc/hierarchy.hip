@@ -49,6 +49,40 @@ Timer::~Timer() {
   for (auto e : ev) (void)hipEventDestroy(e);
 }
 
+void KernelTimer::begin(int k, hipStream_t s) {
+  if (!on) return;
+  if (2 * used + 2 > ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      STMG_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    kind.push_back(0);
+  }
+  kind[used] = k;
+  STMG_HIP(hipEventRecord(ev[2 * used], s));
+}
+void KernelTimer::end(hipStream_t s) {
+  if (!on) return;
+  STMG_HIP(hipEventRecord(ev[2 * used + 1], s));
+  ++used;
+  if (used >= 4096) flush();
+}
+void KernelTimer::flush() {
+  if (used == 0) return;
+  STMG_HIP(hipEventSynchronize(ev[2 * used - 1]));
+  for (size_t i = 0; i < used; ++i) {
+    float ms = 0.f;
+    STMG_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    n[kind[i]] += 1;
+    t[kind[i]] += ms * 1e-3;
+  }
+  used = 0;
+}
+KernelTimer::~KernelTimer() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+}
+
 // ------------------------------------------------------------------ 1D tables
 LevelTables make_level_tables(int p) {
   LevelTables t;
@@ -423,7 +457,9 @@ template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
   hipStream_t s = h->stream;
   long long n = L.nst(h->tm.n_t);
   fill<T>(y, (T)0, n, s);
+  if (level == 0) h->ktimer.begin(0, s);
   st_apply<T>(L.g, L.lt, tdev<T>(h), x, y, (T)1, s);
+  if (level == 0) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)1, x, (T)0, y, s);
 }
 
@@ -432,7 +468,10 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
   hipStream_t s = h->stream;
   long long n = L.nst(h->tm.n_t);
   copy<T>(f, r, n, s);
+  bool fine = (&L == h->levels[0].get());
+  if (fine) h->ktimer.begin(0, s);
   st_apply<T>(L.g, L.lt, tdev<T>(h), u, r, (T)-1, s);
+  if (fine) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)-1, u, (T)1, r, s);
 }
 
@@ -440,8 +479,11 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
 template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u) {
   LevelData<T>& d = ldata<T>(L);
   h->timer.mark(TB_SMOOTH, h->stream);
+  bool fine = (&L == h->levels[0].get());
+  if (fine) h->ktimer.begin(1, h->stream);
   asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
                (T)L.omega, h->stream);
+  if (fine) h->ktimer.end(h->stream);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)L.omega, r, (T)1, u, h->stream);
   h->timer.mark(TB_GMG, h->stream);
 }
@@ -601,7 +643,9 @@ std::vector<std::complex<double>> hessenberg_eigs(const hm::Mat& H0) {
 }  // namespace
 
 // omega_l = 2 / (lambda_max + lambda_min) of ASM * S (eq. relaxation), from the real parts of
-// the Ritz values of 15 Arnoldi steps with a deterministic start vector, clamped to (0, 1]
+// the Ritz values of 15 Arnoldi steps with a deterministic start vector, clamped to (0, 1];
+// with a negative omega in the configuration, omega_l = |omega| / lambda_max instead (a
+// smoothing-oriented choice that damps the top of the spectrum, see the header)
 void estimate_omegas(stmg_handle* h) {
   hipStream_t s = h->stream;
   const int steps = 15;
@@ -662,7 +706,8 @@ void estimate_omegas(stmg_handle* h) {
     auto ev = hessenberg_eigs(Hm);
     double lmax = -1e300, lmin = 1e300;
     for (auto& e : ev) { lmax = std::max(lmax, e.real()); lmin = std::min(lmin, e.real()); }
-    double om = 2.0 / (lmax + lmin);
+    // eq. relaxation (omega field == 0); omega field < 0 selects |omega| / lambda_max instead
+    double om = h->cfg.omega < 0.0 ? -h->cfg.omega / lmax : 2.0 / (lmax + lmin);
     if (!std::isfinite(om)) om = 1.0;
     L.omega = std::min(1.0, std::max(1e-3, om));
   }

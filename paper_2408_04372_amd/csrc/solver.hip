@@ -54,6 +54,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   stmg_solve_info inf{};
   h->timer.on = true;
   h->timer.reset();
+  h->ktimer.on = true;
   h->timer.mark(TB_OTHER, s);
   // homogeneous Dirichlet data: zero b and x on the boundary
   copy<double>(b_in, b, n, s);
@@ -61,10 +62,10 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   boundary_axpby<double>(L.bidx.as<int>(), L.nb, L.g.nx, n_t, 0.0, x, 0.0, x, s);
   norm2_check<double>(b, n, dots, red, s);
   std::vector<double> nb2 = download<double>(dots, 2, s);
-  if (nb2[1] != 0.0) { h->timer.on = false; fail(STMG_E_NONFINITE, "right-hand side contains NaN or Inf"); }
+  if (nb2[1] != 0.0) { h->timer.on = false; h->ktimer.on = false; fail(STMG_E_NONFINITE, "right-hand side contains NaN or Inf"); }
   norm2_check<double>(x, n, dots, red, s);
   std::vector<double> nx2 = download<double>(dots, 2, s);
-  if (nx2[1] != 0.0) { h->timer.on = false; fail(STMG_E_NONFINITE, "initial guess contains NaN or Inf"); }
+  if (nx2[1] != 0.0) { h->timer.on = false; h->ktimer.on = false; fail(STMG_E_NONFINITE, "initial guess contains NaN or Inf"); }
   const double bnorm = std::sqrt(nb2[0]);
   stmg_status status = STMG_OK;
   int it = 0;
@@ -169,6 +170,8 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   double buckets[4] = {0, 0, 0, 0};
   h->timer.accumulate(buckets);
   h->timer.on = false;
+  h->ktimer.flush();
+  h->ktimer.on = false;
   inf.iterations = it;
   inf.rel_residual = rel;
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -40,7 +40,7 @@ class Config:
     n_smooth: int = 1
     min_p: int = 1
     coarse_cells: int = 2
-    omega: float = 0.0           # <= 0: estimate per level
+    omega: float = 0.0           # > 0 fixed; 0: eq. relaxation per level; < 0: |omega| / lambda_max per level
     precision: int = PREC_FP64
     restart: int = 30
     max_iter: int = 200

@@ -121,12 +121,13 @@ def test_vcycle(name):
             assert rel_err(_np(z), ref) < tol, dt
 
 
+@pytest.mark.parametrize("rule", [0.0, -1.0])
 @pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2"])
-def test_omega_estimate(name):
+def test_omega_estimate(name, rule):
     cfg, verts, coef = problem(name)
     op = oracle_op(cfg, verts, coef)
-    H = mg.Hierarchy(op)
-    with _handle(cfg, verts, coef, omega=0.0) as h:
+    H = mg.Hierarchy(op, omega_rule=rule)
+    with _handle(cfg, verts, coef, omega=rule) as h:
         L = h.info["n_levels"]
         got = h.info["omega"][: L - 1]
         ref = [H.levels[L - 1 - l].omega for l in range(L - 1)]
