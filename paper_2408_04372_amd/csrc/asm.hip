@@ -12,7 +12,9 @@
 //     B_K^{-1} = (I (x) Q) blockdiag_s (lambda_s M_tau + N~)^{-1} (I (x) Q^T),
 // so one application per spatial cell is two dense [n_s x n_s] x [n_s x n_t]
 // products (all time cells of the slab at once) and n_s tiny N_t x N_t solves,
-// instead of a dense (N_t n_s)^2 inverse per block.  Dirichlet nodes inside a
+// instead of a dense (N_t n_s)^2 inverse per block.  Blocks are applied in 2^d
+// colours of cells that share no node, so corrections are added without atomics.
+// Dirichlet nodes inside a
 // block are decoupled (identity rows in A_KK and M_KK) and masked on input and
 // output, so they never receive a correction from the block.
 //
@@ -133,7 +135,7 @@ constexpr int JMAX = 32;   // accumulators per thread
 
 // u += omega * sum_K R_K^T B_K^{-1} R_K r   (interior rows; one workgroup per spatial cell)
 template <class T>
-__global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, int n_t, int nt_cell,
+__global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, ColourSet cs, int n_t, int nt_cell,
                                                    const T* __restrict__ Q, const T* __restrict__ Tinv,
                                                    const T* __restrict__ r, T* __restrict__ u, T omega,
                                                    int nblocks) {
@@ -141,10 +143,10 @@ __global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, int n_t, int nt_c
   const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
   T* R = reinterpret_cast<T*>(smem_raw);     // [n_t][ns]
   T* W = R + (size_t)n_t * ns;               // [n_t][ns]
-  const long long cell = xcd_swizzle(blockIdx.x, nblocks);
-  if (cell >= g.ncells) return;
+  const long long li = xcd_swizzle(blockIdx.x, nblocks);
+  if (li >= cs.count) return;
   int cx, cy, cz;
-  cell_coords(cell, g, cx, cy, cz);
+  const long long cell = colour_cell(cs, g, li, cx, cy, cz);
   const int tid = threadIdx.x;
   for (int idx = tid; idx < n_t * ns; idx += ABS) {
     int j = idx / ns, a = idx - j * ns;
@@ -212,9 +214,185 @@ __global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, int n_t, int nt_c
 #pragma unroll
       for (int jj = 0; jj < JMAX; ++jj) {
         int j = jg + jj * JG;
-        if (j < n_t) atomic_add(u + (long long)j * g.nx + node, omega * acc[jj]);
+        if (j < n_t) u[(long long)j * g.nx + node] += omega * acc[jj];
       }
     }
+  }
+}
+
+
+// ---- MFMA variant --------------------------------------------------------------------------
+// 16x16x4 matrix-core products (FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32).
+// Fragment layout on gfx950: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the 16x16
+// result D[i][j] sits in lane j + 16 (i % 4), register i / 4 for FP64 and in lane
+// j + 16 (i / 4), register i % 4 for FP32.
+template <class T> struct Mma;
+template <> struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 fma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 fma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <class T, int NT>
+__device__ inline void temporal_modes(T* P, int LD, const T* __restrict__ Tinv, long long cell, int ns,
+                                      int n_t, int tid) {
+  const int c = n_t / NT;
+  for (int idx = tid; idx < c * ns; idx += 256) {
+    int s = idx / c, m = idx - s * c;
+    const T* Ti = Tinv + ((size_t)cell * ns + s) * NT * NT;
+    T w[NT];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) w[b] = P[s * LD + m * NT + b];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      T sacc = 0;
+#pragma unroll
+      for (int b = 0; b < NT; ++b) sacc += Ti[a * NT + b] * w[b];
+      P[s * LD + m * NT + a] = sacc;
+    }
+  }
+}
+
+constexpr int MAXM = 2;    // M tiles per wave (NSP <= 128)
+constexpr int MAXNT = 2;    // N tiles (NTP <= 32)
+constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
+
+// Same map as k_asm_apply, with both products on the matrix cores.  LDS holds one
+// [NSP][NTP + 1] panel: R^T (B operand of W = Q^T R^T), then W (B operand of Z = Q W),
+// then Z for the write-back.  Wave w owns the M tiles w, w + 4 and every N tile, and
+// loads its whole A strip (all K steps) before issuing the products.  Global traffic
+// walks the lattice with the node index fastest.
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_asm_mfma(GeomDesc g, ColourSet cs, int n_t, int nt_cell, int NSP,
+                                                  int NTP, const T* __restrict__ Q,
+                                                  const T* __restrict__ Tinv, const T* __restrict__ r,
+                                                  T* __restrict__ u, T omega, int nblocks) {
+  typedef typename Mma<T>::v4 v4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* P = reinterpret_cast<T*>(smem_raw);    // [NSP][LD]
+  const int LD = NTP + 1;
+  const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
+  const long long li = xcd_swizzle(blockIdx.x, nblocks);
+  if (li >= cs.count) return;
+  int cx, cy, cz;
+  const long long cell = colour_cell(cs, g, li, cx, cy, cz);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // P = R^T (zero padded; Dirichlet nodes read as zero), node index fastest
+  for (int idx = tid; idx < NTP * NSP; idx += 256) {
+    int j = idx / NSP, a = idx - j * NSP;
+    T v = 0;
+    if (a < ns && j < n_t) {
+      bool in;
+      long long node = node_of(g, cx, cy, cz, a, in);
+      if (in) v = r[(long long)j * g.nx + node];
+    }
+    P[a * LD + j] = v;
+  }
+  __syncthreads();
+  const T* Qc = Q + (size_t)cell * ns * ns;    // column-major: Q(a, s) = Qc[s * ns + a]
+  const int MT = NSP / 16, NTt = NTP / 16, KS = NSP / 4;
+  const int li16 = lane & 15, lk = lane >> 4;
+  v4 acc[MAXM][MAXNT];
+  // W[s][j] = sum_a Q(a, s) R^T[a][j]
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) {
+    int mt = wave + 4 * q;
+#pragma unroll
+    for (int nt = 0; nt < MAXNT; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
+    if (mt >= MT) continue;
+    int s_idx = mt * 16 + li16;
+    T av[MAXK];
+    const T* qcol = Qc + (size_t)(s_idx < ns ? s_idx : 0) * ns;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+      int a_idx = 4 * k + lk;
+      av[k] = (k < KS && s_idx < ns && a_idx < ns) ? qcol[a_idx] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+      if (k < KS) {
+        const T* prow = P + (4 * k + lk) * LD + li16;
+#pragma unroll
+        for (int nt = 0; nt < MAXNT; ++nt)
+          if (nt < NTt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) {
+    int mt = wave + 4 * q;
+    if (mt >= MT) continue;
+#pragma unroll
+    for (int nt = 0; nt < MAXNT; ++nt) {
+      if (nt >= NTt) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
+    }
+  }
+  __syncthreads();
+  // per mode s and time cell m: W[s, m, :] <- (lambda_s M_tau + N~)^{-1} W[s, m, :]
+  switch (nt_cell) {
+    case 1: temporal_modes<T, 1>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    case 2: temporal_modes<T, 2>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    case 3: temporal_modes<T, 3>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    case 4: temporal_modes<T, 4>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    case 5: temporal_modes<T, 5>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    default: temporal_modes<T, 6>(P, LD, Tinv, cell, ns, n_t, tid); break;
+  }
+  __syncthreads();
+  // Z[a][j] = sum_s Q(a, s) W[s][j]
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) {
+    int mt = wave + 4 * q;
+#pragma unroll
+    for (int nt = 0; nt < MAXNT; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
+    if (mt >= MT) continue;
+    int a_idx = mt * 16 + li16;
+    T av[MAXK];
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+      int s_idx = 4 * k + lk;
+      av[k] = (k < KS && a_idx < ns && s_idx < ns) ? Qc[(size_t)s_idx * ns + a_idx] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+      if (k < KS) {
+        const T* prow = P + (4 * k + lk) * LD + li16;
+#pragma unroll
+        for (int nt = 0; nt < MAXNT; ++nt)
+          if (nt < NTt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
+      }
+    }
+  }
+  __syncthreads();
+  // Z into LDS, then added to the interior nodes with the node index fastest
+#pragma unroll
+  for (int q = 0; q < MAXM; ++q) {
+    int mt = wave + 4 * q;
+    if (mt >= MT) continue;
+#pragma unroll
+    for (int nt = 0; nt < MAXNT; ++nt) {
+      if (nt >= NTt) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n_t * ns; idx += 256) {
+    int j = idx / ns, a = idx - j * ns;
+    bool in;
+    long long node = node_of(g, cx, cy, cz, a, in);
+    if (in) u[(long long)j * g.nx + node] += omega * P[a * LD + j];
   }
 }
 
@@ -261,9 +439,22 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
   if ((n_t + JG - 1) / JG > JMAX) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the smoother kernel");
   if (nt_cell > 8) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs per time cell");
   size_t lds = sizeof(T) * 2 * (size_t)n_t * ns;
-  int nb = (int)g.ncells;
-  hipLaunchKernelGGL(k_asm_apply<T>, dim3(nb), dim3(ABS), lds, s, g, n_t, nt_cell, Q, Tinv, r, u, omega, nb);
-  STMG_CHECK_LAUNCH();
+  const int NSP = (ns + 15) / 16 * 16, NTP = (n_t + 15) / 16 * 16;
+  const bool use_mfma = n_t >= 8 && NSP <= 16 * 4 * MAXM && NTP <= 16 * MAXNT && NSP <= 4 * MAXK &&
+                        nt_cell <= 6;
+  // colours of cells without shared nodes: block corrections are added without atomics
+  for (int colour = 0; colour < n_colours(g.dim); ++colour) {
+    ColourSet cs = colour_set(g, colour);
+    if (cs.count == 0) continue;
+    int nb = (int)cs.count;
+    if (use_mfma)
+      hipLaunchKernelGGL(k_asm_mfma<T>, dim3(nb), dim3(256), sizeof(T) * (size_t)NSP * (NTP + 1), s, g, cs, n_t,
+                         nt_cell, NSP, NTP, Q, Tinv, r, u, omega, nb);
+    else
+      hipLaunchKernelGGL(k_asm_apply<T>, dim3(nb), dim3(ABS), lds, s, g, cs, n_t, nt_cell, Q, Tinv, r, u,
+                         omega, nb);
+    STMG_CHECK_LAUNCH();
+  }
 }
 
 template void asm_tinv<double>(long long, int, int, const double*, const double*, const double*, double*, int*, hipStream_t);

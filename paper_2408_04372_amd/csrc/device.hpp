@@ -50,4 +50,35 @@ __device__ inline int xcd_swizzle(int b, int nb) {
 
 template <class T> __device__ inline void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
 
+// Cells of one colour (cx % 2, cy % 2, cz % 2) = (colour & 1, colour >> 1 & 1, colour >> 2 & 1)
+// share no lattice node, so a launch over one colour may update its nodes without atomics.
+struct ColourSet {
+  int colour = 0;
+  int m[3] = {1, 1, 1};   // cells of this parity per direction
+  long long count = 0;
+};
+inline ColourSet colour_set(const GeomDesc& g, int colour) {
+  ColourSet c;
+  c.colour = colour;
+  c.count = 1;
+  for (int d = 0; d < 3; ++d) {
+    int o = (colour >> d) & 1;
+    c.m[d] = (d < g.dim) ? (g.nc[d] - o + 1) / 2 : (o ? 0 : 1);
+    c.count *= c.m[d];
+  }
+  return c;
+}
+__device__ inline long long colour_cell(const ColourSet& cs, const GeomDesc& g, long long li, int& cx,
+                                        int& cy, int& cz) {
+  int ix = (int)(li % cs.m[0]);
+  long long r = li / cs.m[0];
+  int iy = (int)(r % cs.m[1]);
+  int iz = (int)(r / cs.m[1]);
+  cx = 2 * ix + (cs.colour & 1);
+  cy = 2 * iy + ((cs.colour >> 1) & 1);
+  cz = 2 * iz + ((cs.colour >> 2) & 1);
+  return ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+inline int n_colours(int dim) { return dim == 3 ? 8 : 4; }
+
 }  // namespace stmg

@@ -3,8 +3,9 @@
 // factorisation; the temporal factors are small dense matrices and A_h u^i,
 // M_h u^i are formed once per temporal DoF and reused).
 //
-// MI355X mapping.  One 64-lane wave per workgroup.  A "team" of p+1 lanes owns
-// one (spatial cell, output temporal DoF i) pair; lane t of the team holds the
+// MI355X mapping.  A workgroup covers every output temporal DoF of a few cells in
+// one round.  A "team" of p+1 lanes owns one (spatial cell, output temporal DoF i)
+// pair; lane t of the team holds the
 // z = t plane of the cell in registers ("XY layout": x and y sweeps are lane
 // local) or, after a transpose through LDS, the y = t plane ("XZ layout": x and
 // z sweeps are lane local).  The temporal mixing is done at the nodes while
@@ -13,8 +14,10 @@
 //   values at Gauss points by S-sweeps, reference gradients by collocation
 //   D-sweeps on the Gauss points, geometry factors (per quadrature point,
 //   computed once per cell into LDS), and the transposed sweeps back.
-// Contributions are scatter-added with hardware FP atomics.  In 2D a team is a
-// single lane holding the whole cell.
+// Each cell's space-time values are staged once in LDS (coalesced loads), and
+// cells are processed in 2^d colours of cells that share no node, so every
+// contribution is added with a plain read-modify-write (no atomics; results are
+// bitwise reproducible).  In 2D a team is a single lane holding the whole cell.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -207,171 +210,171 @@ __device__ inline void xz_to_xy(T* scr, int t, const T (&in)[N][N], T (&out)[N][
 }
 
 template <class T, int N>
-__global__ __launch_bounds__(64) void st_apply3(OpArgs<T, N> A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void st_apply3(OpArgs<T, N> A,
+                                                                                       ColourSet cs) {
   constexpr int NQ = N * N * N;
-  constexpr int TPW = 64 / N;
   constexpr int GS = 7;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n_t = A.tp.n_t;
+  const int cpw = A.cpw;
   T* geo = reinterpret_cast<T*>(smem_raw);                  // [cpw][NQ][GS]
-  T* scr_all = geo + (size_t)A.cpw * NQ * GS;               // [TPW + 1][NQ] (last: idle lanes)
+  T* xs = geo + (size_t)cpw * NQ * GS;                      // [cpw][n_t][NQ] + dummy panel: input, scratch, output
   const GeomDesc& g = A.g;
   const int p = N - 1;
-  const int lane = threadIdx.x;
-  const int team = lane / N;
-  const int t = lane - team * N;
-  const bool lane_ok = team < TPW;
-  T* scr = scr_all + (size_t)(lane_ok ? team : TPW) * NQ;
-
-  const int blk = xcd_swizzle(blockIdx.x, A.nblocks);
-  const long long cell0 = (long long)blk * A.cpw;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int team = tid / N;                                  // one team per (local cell, output i)
+  const int t = tid - team * N;
+  const int items = cpw * n_t;
+  const long long plane = g.nx;
+  const long long li0 = (long long)xcd_swizzle(blockIdx.x, A.nblocks) * cpw;
+  const int ncell = (int)((cs.count - li0) < cpw ? (cs.count - li0) : cpw);
 
   // geometry factors of this block's cells
-  for (int idx = lane; idx < A.cpw * NQ; idx += 64) {
+  for (int idx = tid; idx < ncell * NQ; idx += nthr) {
     int lc = idx / NQ, q = idx - lc * NQ;
-    long long cell = cell0 + lc;
-    if (cell >= g.ncells) continue;
-    int cx = (int)(cell % g.nc[0]);
-    int cy = (int)((cell / g.nc[0]) % g.nc[1]);
-    int cz = (int)(cell / ((long long)g.nc[0] * g.nc[1]));
+    int cx, cy, cz;
+    long long cell = colour_cell(cs, g, li0 + lc, cx, cy, cz);
     int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
     double o[7];
     geometry<3, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, cz, qx, qy, qz, q, o);
     T* dst = geo + ((size_t)lc * NQ + q) * GS;
 #pragma unroll
-    for (int s = 0; s < GS; ++s) dst[s] = (T)o[s];
+    for (int s2 = 0; s2 < GS; ++s2) dst[s2] = (T)o[s2];
+  }
+  // stage every temporal plane of the cells (Dirichlet nodes read as zero), node index fastest
+  for (int lc = 0; lc < ncell; ++lc) {
+    int cx, cy, cz;
+    colour_cell(cs, g, li0 + lc, cx, cy, cz);
+    T* dst = xs + (size_t)lc * n_t * NQ;
+    for (int idx = tid; idx < n_t * NQ; idx += nthr) {
+      int j = idx / NQ, node = idx - j * NQ;
+      int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
+      int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+      bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 && gz != g.nn[2] - 1;
+      dst[idx] = in ? A.x[(long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx] : (T)0;
+    }
   }
   __syncthreads();
 
-  const int n_t = A.tp.n_t;
-  const int items = A.cpw * n_t;
-  const long long plane = g.nx;
-  for (int it0 = 0; it0 < items; it0 += TPW) {
-    const int item = it0 + team;
-    const int lc = item / n_t;
-    const int i = item - lc * n_t;
-    const long long cell = cell0 + lc;
-    const bool act = lane_ok && item < items && cell < g.ncells;
-    int cx = 0, cy = 0, cz = 0;
-    if (act) {
-      cx = (int)(cell % g.nc[0]);
-      cy = (int)((cell / g.nc[0]) % g.nc[1]);
-      cz = (int)(cell / ((long long)g.nc[0] * g.nc[1]));
-    }
-    // node offsets and interior mask of this lane's z-plane
-    const int gz = cz * p + t;
-    const bool zb = (gz == 0) || (gz == g.nn[2] - 1);
-    long long base = ((long long)gz * g.nn[1] + (long long)cy * p) * g.nn[0] + (long long)cx * p;
-    bool inner[N][N];
+  const int lc = team / (n_t > 0 ? n_t : 1);
+  const int i = team - lc * n_t;
+  const bool act = team < items && lc < ncell;
+  // temporal mixing from LDS: a = (M_T x)_i (stiffness input), b = (N_T x)_i (mass input); lane t = z plane
+  T a[N][N], b[N][N];
 #pragma unroll
-    for (int y = 0; y < N; ++y)
+  for (int y = 0; y < N; ++y)
 #pragma unroll
-      for (int x = 0; x < N; ++x) {
-        int gy = cy * p + y, gx = cx * p + x;
-        inner[y][x] = act && !zb && gy != 0 && gy != g.nn[1] - 1 && gx != 0 && gx != g.nn[0] - 1;
-      }
-
-    // gather with temporal mixing: a = (M_T x)_i (stiffness input), b = (N_T x)_i (mass input)
-    T a[N][N], b[N][N];
-#pragma unroll
-    for (int y = 0; y < N; ++y)
-#pragma unroll
-      for (int x = 0; x < N; ++x) { a[y][x] = 0; b[y][x] = 0; }
-    if (act) {
-      for (int k = A.tp.mptr[i]; k < A.tp.mptr[i + 1]; ++k) {
-        const T c = A.tp.mval[k];
-        const T* xj = A.x + (long long)A.tp.mcol[k] * plane + base;
-#pragma unroll
-        for (int y = 0; y < N; ++y)
-#pragma unroll
-          for (int x = 0; x < N; ++x)
-            if (inner[y][x]) a[y][x] += c * xj[(long long)y * g.nn[0] + x];
-      }
-      for (int k = A.tp.nptr[i]; k < A.tp.nptr[i + 1]; ++k) {
-        const T c = A.tp.nval[k];
-        const T* xj = A.x + (long long)A.tp.ncol[k] * plane + base;
-#pragma unroll
-        for (int y = 0; y < N; ++y)
-#pragma unroll
-          for (int x = 0; x < N; ++x)
-            if (inner[y][x]) b[y][x] += c * xj[(long long)y * g.nn[0] + x];
-      }
-    }
-
-    const auto& S = A.tab.S;
-    const auto& D = A.tab.D;
-    T t0[N][N], t1[N][N], t2[N][N];
-
-    // mass path: b -> values at Gauss points (x, y in XY layout, z after transpose)
-    cols<T, N>(S, b, t0);                 // [y][qx]
-    rows<T, N>(S, t0, b);                 // [qy][qx]
-    xy_to_xz<T, N>(scr, t, b, t0);        // lane = qy : [z][qx]
-    T u[N][N];
-    rows<T, N>(S, t0, u);                 // [qz][qx] values of b
-    // u <- m = |det J| w * b_hat
-    const T* gcell = geo + (size_t)(act ? lc : 0) * NQ * GS;
-#pragma unroll
-    for (int qz = 0; qz < N; ++qz)
-#pragma unroll
-      for (int qx = 0; qx < N; ++qx) u[qz][qx] *= gcell[((qz * N + t) * N + qx) * GS + 6];
-
-    // stiffness path: a -> values and y-derivative at Gauss points (XY), then XZ
-    cols<T, N>(S, a, t0);                 // [y][qx]
-    rows<T, N>(S, t0, t1);                // [qy][qx] values
-    rows<T, N>(D, t1, t2);                // [qy][qx] d/dy
-    xy_to_xz<T, N>(scr, t, t1, t0);       // values  [z][qx]
-    xy_to_xz<T, N>(scr, t, t2, t1);       // dy      [z][qx]
-    rows<T, N>(S, t0, a);                 // a  = values at (qx, qy=t, qz)
-    rows<T, N>(S, t1, b);                 // b  = d/dy at Gauss points (reuse register set)
-
-    // quadrature-point operation; accumulate the x/z-derivative transposes into u
-#pragma unroll
-    for (int qz = 0; qz < N; ++qz)
-#pragma unroll
-      for (int qx = 0; qx < N; ++qx) {
-        T dx = 0, dz = 0;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          dx += D[qx][r] * a[qz][r];
-          dz += D[qz][r] * a[r][qx];
-        }
-        const T dy = b[qz][qx];
-        const T* G = gcell + ((qz * N + t) * N + qx) * GS;
-        const T gx = G[0] * dx + G[1] * dy + G[2] * dz;
-        const T gy = G[1] * dx + G[3] * dy + G[4] * dz;
-        const T gz = G[2] * dx + G[4] * dy + G[5] * dz;
-        t2[qz][qx] = gy;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          u[qz][r] += D[qx][r] * gx;
-          u[r][qx] += D[qz][r] * gz;
-        }
-      }
-    // integrate in z (XZ layout), then back to XY for y and x
-    rows_t<T, N>(S, u, t0);               // [z][qx]
-    rows_t<T, N>(S, t2, t1);              // gy integrated in z: [z][qx]
-    xz_to_xy<T, N>(scr, t, t0, u);        // lane = z: [qy][qx]
-    xz_to_xy<T, N>(scr, t, t1, t2);       // [qy][qx]
-    rows_t<T, N>(D, t2, t0);              // d/dy transpose
-#pragma unroll
-    for (int qy = 0; qy < N; ++qy)
-#pragma unroll
-      for (int qx = 0; qx < N; ++qx) u[qy][qx] += t0[qy][qx];
-    rows_t<T, N>(S, u, t1);               // [y][qx]
-    cols_t<T, N>(S, t1, t2);              // [y][x]
-
-    if (act) {
-      T* yi = A.y + (long long)i * plane + base;
+    for (int x = 0; x < N; ++x) { a[y][x] = 0; b[y][x] = 0; }
+  if (act) {
+    const T* xc = xs + (size_t)lc * n_t * NQ + t * N * N;
+    for (int k = A.tp.mptr[i]; k < A.tp.mptr[i + 1]; ++k) {
+      const T c = A.tp.mval[k];
+      const T* xj = xc + (size_t)A.tp.mcol[k] * NQ;
 #pragma unroll
       for (int y = 0; y < N; ++y)
 #pragma unroll
-        for (int x = 0; x < N; ++x)
-          if (inner[y][x]) atomic_add(yi + (long long)y * g.nn[0] + x, A.scale * t2[y][x]);
+        for (int x = 0; x < N; ++x) a[y][x] += c * xj[y * N + x];
+    }
+    for (int k = A.tp.nptr[i]; k < A.tp.nptr[i + 1]; ++k) {
+      const T c = A.tp.nval[k];
+      const T* xj = xc + (size_t)A.tp.ncol[k] * NQ;
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x) b[y][x] += c * xj[y * N + x];
+    }
+  }
+  __syncthreads();                                           // staged input no longer needed
+  // the input panel of (lc, i) becomes this team's transpose scratch and finally its output;
+  // lanes without an item (partial last block, lanes past the last team) use a dummy panel
+  T* scr = xs + (size_t)(act ? team : items) * NQ;
+  const int ts = t;
+
+  const auto& S = A.tab.S;
+  const auto& D = A.tab.D;
+  T t0[N][N], t1[N][N], t2[N][N];
+
+  // mass path: b -> values at Gauss points (x, y in XY layout, z after transpose)
+  cols<T, N>(S, b, t0);                 // [y][qx]
+  rows<T, N>(S, t0, b);                 // [qy][qx]
+  xy_to_xz<T, N>(scr, ts, b, t0);       // lane = qy : [z][qx]
+  T u[N][N];
+  rows<T, N>(S, t0, u);                 // [qz][qx] values of b
+  const T* gcell = geo + (size_t)(act ? lc : 0) * NQ * GS;
+#pragma unroll
+  for (int qz = 0; qz < N; ++qz)
+#pragma unroll
+    for (int qx = 0; qx < N; ++qx) u[qz][qx] *= gcell[((qz * N + ts) * N + qx) * GS + 6];
+
+  // stiffness path: a -> values and y-derivative at Gauss points (XY), then XZ
+  cols<T, N>(S, a, t0);                 // [y][qx]
+  rows<T, N>(S, t0, t1);                // [qy][qx] values
+  rows<T, N>(D, t1, t2);                // [qy][qx] d/dy
+  xy_to_xz<T, N>(scr, ts, t1, t0);      // values  [z][qx]
+  xy_to_xz<T, N>(scr, ts, t2, t1);      // dy      [z][qx]
+  rows<T, N>(S, t0, a);                 // a  = values at (qx, qy=t, qz)
+  rows<T, N>(S, t1, b);                 // b  = d/dy at Gauss points
+
+  // quadrature-point operation; accumulate the x/z-derivative transposes into u
+#pragma unroll
+  for (int qz = 0; qz < N; ++qz)
+#pragma unroll
+    for (int qx = 0; qx < N; ++qx) {
+      T dx = 0, dz = 0;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        dx += D[qx][r] * a[qz][r];
+        dz += D[qz][r] * a[r][qx];
+      }
+      const T dy = b[qz][qx];
+      const T* G = gcell + ((qz * N + ts) * N + qx) * GS;
+      const T gx = G[0] * dx + G[1] * dy + G[2] * dz;
+      const T gy = G[1] * dx + G[3] * dy + G[4] * dz;
+      const T gz = G[2] * dx + G[4] * dy + G[5] * dz;
+      t2[qz][qx] = gy;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        u[qz][r] += D[qx][r] * gx;
+        u[r][qx] += D[qz][r] * gz;
+      }
+    }
+  // integrate in z (XZ layout), then back to XY for y and x
+  rows_t<T, N>(S, u, t0);               // [z][qx]
+  rows_t<T, N>(S, t2, t1);              // gy integrated in z: [z][qx]
+  xz_to_xy<T, N>(scr, ts, t0, u);       // lane = z: [qy][qx]
+  xz_to_xy<T, N>(scr, ts, t1, t2);      // [qy][qx]
+  rows_t<T, N>(D, t2, t0);              // d/dy transpose
+#pragma unroll
+  for (int qy = 0; qy < N; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < N; ++qx) u[qy][qx] += t0[qy][qx];
+  rows_t<T, N>(S, u, t1);               // [y][qx]
+  cols_t<T, N>(S, t1, t2);              // [y][x]
+  // cell output (node order) into the team's panel, then one coalesced pass over the block
+  if (act) {
+#pragma unroll
+    for (int y = 0; y < N; ++y)
+#pragma unroll
+      for (int x = 0; x < N; ++x) scr[(t * N + y) * N + x] = t2[y][x];
+  }
+  __syncthreads();
+  for (int lc2 = 0; lc2 < ncell; ++lc2) {
+    int cx, cy, cz;
+    colour_cell(cs, g, li0 + lc2, cx, cy, cz);
+    const T* src = xs + (size_t)lc2 * n_t * NQ;
+    for (int idx = tid; idx < n_t * NQ; idx += nthr) {
+      int j = idx / NQ, node = idx - j * NQ;
+      int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
+      int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+      bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 && gz != g.nn[2] - 1;
+      if (in) A.y[(long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx] += A.scale * src[idx];
     }
   }
 }
 
 template <class T, int N>
-__global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A) {
+__global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A, ColourSet cs) {
   constexpr int NQ = N * N;
   constexpr int GS = 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -379,13 +382,12 @@ __global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A) {
   const GeomDesc& g = A.g;
   const int p = N - 1;
   const int lane = threadIdx.x;
-  const int blk = xcd_swizzle(blockIdx.x, A.nblocks);
-  const long long cell0 = (long long)blk * A.cpw;
+  const long long li0 = (long long)xcd_swizzle(blockIdx.x, A.nblocks) * A.cpw;
   for (int idx = lane; idx < A.cpw * NQ; idx += 64) {
     int lc = idx / NQ, q = idx - lc * NQ;
-    long long cell = cell0 + lc;
-    if (cell >= g.ncells) continue;
-    int cx = (int)(cell % g.nc[0]), cy = (int)(cell / g.nc[0]);
+    if (li0 + lc >= cs.count) continue;
+    int cx, cy, cz;
+    long long cell = colour_cell(cs, g, li0 + lc, cx, cy, cz);
     double o[7];
     geometry<2, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, 0, q % N, q / N, 0, q, o);
     T* dst = geo + ((size_t)lc * NQ + q) * GS;
@@ -400,9 +402,9 @@ __global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A) {
     const int item = it0 + lane;
     const int lc = item / n_t;
     const int i = item - lc * n_t;
-    const long long cell = cell0 + lc;
-    if (item >= items || cell >= g.ncells) continue;
-    const int cx = (int)(cell % g.nc[0]), cy = (int)(cell / g.nc[0]);
+    if (item >= items || li0 + lc >= cs.count) continue;
+    int cx, cy, cz;
+    colour_cell(cs, g, li0 + lc, cx, cy, cz);
     long long base = (long long)cy * p * g.nn[0] + (long long)cx * p;
     bool inner[N][N];
 #pragma unroll
@@ -471,7 +473,7 @@ __global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A) {
     for (int y = 0; y < N; ++y)
 #pragma unroll
       for (int x = 0; x < N; ++x)
-        if (inner[y][x]) atomic_add(yi + (long long)y * g.nn[0] + x, A.scale * ah[y][x]);
+        if (inner[y][x]) yi[(long long)y * g.nn[0] + x] += A.scale * ah[y][x];
   }
 }
 
@@ -513,21 +515,39 @@ void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>
   A.x = x;
   A.y = y;
   A.scale = scale;
+  size_t lds;
+  int threads = 64;
   if (g.dim == 3) {
     constexpr int NQ = N * N * N;
-    int teams = 64 / N;
-    A.cpw = pick_cpw(teams, tp.n_t);
-    A.nblocks = ceil_div(g.ncells, A.cpw);
-    size_t lds = sizeof(T) * ((size_t)A.cpw * NQ * 7 + (size_t)(teams + 1) * NQ);
-    hipLaunchKernelGGL((st_apply3<T, N>), dim3(A.nblocks), dim3(64), lds, s, A);
+    // all n_t outputs of cpw cells in one round: cpw * n_t teams of N lanes, at most 256 lanes
+    int per_cell = N * tp.n_t;
+    if (per_cell > 256) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the operator kernel");
+    int best = 1;
+    double be = -1.0;
+    for (int c = 1; c * per_cell <= 256; ++c) {
+      int lanes = c * per_cell;
+      int th = (lanes + 63) / 64 * 64;
+      double eff = (double)lanes / th;
+      size_t l = sizeof(T) * ((size_t)c * NQ * (7 + tp.n_t) + NQ);
+      if (l > 64 * 1024) break;
+      if (eff > be + 1e-9) { be = eff; best = c; }
+    }
+    A.cpw = best;
+    threads = (A.cpw * per_cell + 63) / 64 * 64;
+    lds = sizeof(T) * ((size_t)A.cpw * NQ * (7 + tp.n_t) + NQ);
   } else {
     constexpr int NQ = N * N;
     A.cpw = pick_cpw(64, tp.n_t);
-    A.nblocks = ceil_div(g.ncells, A.cpw);
-    size_t lds = sizeof(T) * ((size_t)A.cpw * NQ * 4);
-    hipLaunchKernelGGL((st_apply2<T, N>), dim3(A.nblocks), dim3(64), lds, s, A);
+    lds = sizeof(T) * ((size_t)A.cpw * NQ * 4);
   }
-  STMG_CHECK_LAUNCH();
+  for (int colour = 0; colour < n_colours(g.dim); ++colour) {
+    ColourSet cs = colour_set(g, colour);
+    if (cs.count == 0) continue;
+    A.nblocks = ceil_div(cs.count, A.cpw);
+    if (g.dim == 3) hipLaunchKernelGGL((st_apply3<T, N>), dim3(A.nblocks), dim3(threads), lds, s, A, cs);
+    else hipLaunchKernelGGL((st_apply2<T, N>), dim3(A.nblocks), dim3(64), lds, s, A, cs);
+    STMG_CHECK_LAUNCH();
+  }
 }
 
 }  // namespace

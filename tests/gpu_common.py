@@ -22,6 +22,14 @@ CASES = {
                                n_cells=(4, 4, 4), tau=0.1, coef="lognormal", coef_sigma=1.0, seed=24),
     "wave3d_q2_cgp1_ragged": si.Config(dim=3, problem=1, time_method=1, p=2, k=1, n_time_cells=2,
                                        n_cells=(3, 2, 5), tau=0.05, perturb=0.1, seed=25),
+    # n_t >= 8: the smoother runs on the matrix cores
+    "heat3d_q4_dg2_c4_pert": si.Config(dim=3, problem=0, time_method=0, p=4, k=2, n_time_cells=4,
+                                       n_cells=(2, 3, 2), tau=0.05, perturb=0.1, coef="lognormal",
+                                       coef_sigma=0.8, seed=26),
+    "wave3d_q3_cgp2_c4": si.Config(dim=3, problem=1, time_method=1, p=3, k=2, n_time_cells=4,
+                                   n_cells=(3, 2, 2), tau=0.05, coef="lognormal", coef_sigma=1.0, seed=27),
+    "heat3d_q2_dg1_c8_ragged": si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=8,
+                                         n_cells=(3, 4, 2), tau=0.05, perturb=0.1, seed=28),
 }
 
 
