@@ -185,6 +185,35 @@ stmg_status stmg_kernel_stats_get(stmg_handle* h, stmg_kernel_stats* out, int re
  * V-cycle data must have been built (vcycle_dtypes). */
 stmg_status stmg_set_precision(stmg_handle* h, int precision);
 
+/* ---- learned preconditioning stage (not part of the paper's method) ----------------
+ * Network C(r) on a finest-level residual r ([n_t][N_x], FP64, 3D only):
+ *   s = sqrt(mean(r^2)); h_0 = r / s (one channel per temporal DoF);
+ *   h_l = relu(conv_l(h_{l-1})) for l < L, h_L = conv_L(h_{L-1});  C(r) = s h_L, zero on
+ *   Dirichlet nodes (C(0) = 0).  conv_l: 3x3x3 taps on the node lattice with zero padding,
+ *   conv(h)[co][v] = b[co] + sum_{tap, ci} W[tap][co][ci] h[ci][v + off(tap)],
+ *   tap = dx + 3 (dy + 3 dz), off = (dx - 1, dy - 1, dz - 1).
+ * Parameters: one FP32 vector, per layer W (27 * C_out * C_in, tap, then C_out, then C_in)
+ * followed by b (C_out).  Activations BF16, products on BF16 matrix cores with FP32
+ * accumulation.  With precision STMG_PREC_LEARNED, stmg_solve uses
+ *   z = C(r) + V(r - S C(r)), or z = V(r) when ||r - S C(r)|| >= ||r|| or C(r) is not finite
+ * (V = FP32 V-cycle); info->cnn_used / cnn_fallbacks count the two cases. */
+
+/* Create (or replace) the network: n_layers in 1..6 convolutions, channels[0..n_layers]
+ * with channels[0] = channels[n_layers] = n_t and every entry in 1..32.  Parameters start at 0. */
+stmg_status stmg_cnn_create(stmg_handle* h, int n_layers, const int32_t* channels);
+/* Number of FP32 parameters of the network. */
+stmg_status stmg_cnn_param_count(stmg_handle* h, int64_t* n);
+/* Copy n host FP32 parameters in (resets the Adam state) / out. Synchronous. */
+stmg_status stmg_cnn_set_params(stmg_handle* h, const float* params, int64_t n);
+stmg_status stmg_cnn_get_params(stmg_handle* h, float* params, int64_t n);
+/* z = C(r) (device FP64 vectors of the finest level).  Synchronous (reads rms(r)). */
+stmg_status stmg_cnn_forward(stmg_handle* h, const double* r, double* z);
+/* grad (host, n floats) = d/dtheta sum(dz * C(r)) with s = rms(r) held fixed. Synchronous. */
+stmg_status stmg_cnn_param_grad(stmg_handle* h, const double* r, const double* dz, float* grad, int64_t n);
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8, rate lr) on L = ||C(r) - e||^2 / ||e||^2;
+ * *loss receives L before the step (may be NULL).  Synchronous. */
+stmg_status stmg_cnn_train_step(stmg_handle* h, const double* r, const double* e, double lr, double* loss);
+
 /* Override the relaxation parameter of one level (omega > 0). */
 stmg_status stmg_set_omega(stmg_handle* h, int level, double omega);
 

@@ -94,6 +94,15 @@ _SIGS = {
     "stmg_set_precision": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "stmg_kernel_stats_get": ([ctypes.c_void_p, ctypes.POINTER(KernelStats), ctypes.c_int], ctypes.c_int),
     "stmg_query": ([ctypes.c_void_p, ctypes.POINTER(Info)], ctypes.c_int),
+    "stmg_cnn_create": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "stmg_cnn_param_count": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "stmg_cnn_set_params": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "stmg_cnn_get_params": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "stmg_cnn_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "stmg_cnn_param_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+                            ctypes.c_int),
+    "stmg_cnn_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "stmg_destroy": ([ctypes.c_void_p], None),
     "stmg_last_error": ([], ctypes.c_char_p),
 }
@@ -255,6 +264,45 @@ class Handle:
         ks = KernelStats()
         _check(self.lib.stmg_kernel_stats_get(self.h, ctypes.byref(ks), 1 if reset else 0))
         return ks.as_dict()
+
+    # -- learned stage
+    def cnn_create(self, channels):
+        arr = (ctypes.c_int32 * len(channels))(*[int(c) for c in channels])
+        _check(self.lib.stmg_cnn_create(self.h, len(channels) - 1, arr))
+        n = ctypes.c_int64()
+        _check(self.lib.stmg_cnn_param_count(self.h, ctypes.byref(n)))
+        self.cnn_nparam = n.value
+        self.cnn_channels = list(channels)
+        return n.value
+
+    def cnn_set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(self.lib.stmg_cnn_set_params(self.h, th.ctypes.data_as(ctypes.c_void_p), th.size))
+
+    def cnn_get_params(self):
+        th = np.empty(self.cnn_nparam, dtype=np.float32)
+        _check(self.lib.stmg_cnn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p), th.size))
+        return th
+
+    def cnn_forward(self, r, z):
+        import torch
+        self._sz(r, 0); self._sz(z, 0)
+        _check(self.lib.stmg_cnn_forward(self.h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+        return z
+
+    def cnn_param_grad(self, r, dz):
+        import torch
+        g = np.empty(self.cnn_nparam, dtype=np.float32)
+        _check(self.lib.stmg_cnn_param_grad(self.h, _ptr(r, torch.float64), _ptr(dz, torch.float64),
+                                            g.ctypes.data_as(ctypes.c_void_p), g.size))
+        return g
+
+    def cnn_train_step(self, r, e, lr: float) -> float:
+        import torch
+        loss = ctypes.c_double()
+        _check(self.lib.stmg_cnn_train_step(self.h, _ptr(r, torch.float64), _ptr(e, torch.float64), float(lr),
+                                            ctypes.byref(loss)))
+        return loss.value
 
     def set_omega(self, level: int, omega: float):
         _check(self.lib.stmg_set_omega(self.h, level, float(omega)))

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "handle.hpp"
 
@@ -239,6 +240,75 @@ stmg_status stmg_set_precision(stmg_handle* h, int precision) {
       h->cfg.precision = precision;
       h->krylov_m = 0;      // workspace layout depends on the precision
     }
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_create(stmg_handle* h, int n_layers, const int32_t* channels) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!channels) stmg::fail(STMG_E_ARG, "channels is NULL");
+    std::vector<int> ch(channels, channels + n_layers + 1);
+    stmg::cnn_create(h, n_layers, ch.data());
+    h->krylov_m = 0;
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_param_count(stmg_handle* h, int64_t* n) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!n) stmg::fail(STMG_E_ARG, "n is NULL");
+    *n = stmg::cnn_param_count(h);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_set_params(stmg_handle* h, const float* params, int64_t n) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!params) stmg::fail(STMG_E_ARG, "params is NULL");
+    stmg::cnn_set_params(h, params, n);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_get_params(stmg_handle* h, float* params, int64_t n) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!params) stmg::fail(STMG_E_ARG, "params is NULL");
+    stmg::cnn_get_params(h, params, n);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_forward(stmg_handle* h, const double* r, double* z) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!r || !z || (const void*)r == (const void*)z) stmg::fail(STMG_E_ARG, "bad r / z");
+    stmg::cnn_forward(h, r, z);
+    STMG_HIP(hipStreamSynchronize(h->stream));
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_param_grad(stmg_handle* h, const double* r, const double* dz, float* grad, int64_t n) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!r || !dz || !grad) stmg::fail(STMG_E_ARG, "NULL argument");
+    if (n != stmg::cnn_param_count(h)) stmg::fail(STMG_E_ARG, "parameter count mismatch");
+    stmg::cnn_param_grad(h, r, dz, grad);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_cnn_train_step(stmg_handle* h, const double* r, const double* e, double lr, double* loss) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!r || !e) stmg::fail(STMG_E_ARG, "NULL argument");
+    if (!(lr > 0.0)) stmg::fail(STMG_E_ARG, "lr must be positive");
+    double l = stmg::cnn_train_step(h, r, e, lr);
+    if (loss) *loss = l;
     return STMG_OK;
   });
 }

@@ -114,6 +114,14 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
 template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* coarse);
 void estimate_omegas(stmg_handle* h);
 stmg_status fgmres(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
+// learned stage (cnn.hip)
+void cnn_create(stmg_handle* h, int n_layers, const int* channels);
+long long cnn_param_count(stmg_handle* h);
+void cnn_set_params(stmg_handle* h, const float* host, long long n);
+void cnn_get_params(stmg_handle* h, float* host, long long n);
+double cnn_forward(stmg_handle* h, const double* r, double* z);
+void cnn_param_grad(stmg_handle* h, const double* r, const double* dz, float* host);
+double cnn_train_step(stmg_handle* h, const double* r, const double* e, double lr);
 template <class T> LevelData<T>& ldata(Level& L);
 template <class T> const TemporalDev<T>& tdev(stmg_handle* h);
 }  // namespace stmg

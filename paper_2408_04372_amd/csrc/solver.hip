@@ -28,6 +28,7 @@ void ensure_workspace(stmg_handle* h, long long n, int m) {
   if (need32) {
     h->Z32.alloc(sizeof(float) * n * m);
     h->tmp32a.alloc(sizeof(float) * n);
+    if (h->cfg.precision == STMG_PREC_LEARNED) h->tmp32b.alloc(sizeof(float) * n);
     h->Z64.alloc(sizeof(double) * n);   // one FP64 scratch vector (cast of z_j)
   } else {
     h->Z64.alloc(sizeof(double) * n * m);
@@ -46,6 +47,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   const int m = h->cfg.restart;
   const bool mixed = h->cfg.precision != STMG_PREC_FP64;
   const bool learned = h->cfg.precision == STMG_PREC_LEARNED;
+  if (learned && !h->cnn) fail(STMG_E_STATE, "precision LEARNED needs a network (stmg_cnn_create)");
   ensure_workspace(h, n, m);
   double* V = h->V.as<double>();
   double* b = h->w.as<double>();
@@ -101,7 +103,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
         h->timer.mark(TB_GMG, s);
         if (mixed) {
           float* z32 = h->Z32.as<float>() + (size_t)j * n;
-          if (learned && h->cnn) {
+          if (learned) {
             bool used = false;
             cnn_precondition(h, vj, h->Z64.as<double>(), vn, &used);
             if (used) inf.cnn_used++; else inf.cnn_fallbacks++;
