@@ -93,6 +93,25 @@ def cpu_baseline(budget_s: float = 15.0):
                       f"setup {setup:.1f} s excluded"}
 
 
+def copy_probe(nbytes: int = 1 << 30, reps: int = 10):
+    """Plain device-to-device copy of a known size: its FETCH_SIZE / WRITE_SIZE readings per
+    dispatch calibrate the counters against nbytes read and nbytes written."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"copy_bytes": nbytes, "avg_s": t, "GBs_read_plus_write": 2 * nbytes / t / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +120,13 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 10 device copies of 1 GiB (calibration of hardware byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the slab solver is a single-GPU build); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -168,6 +193,28 @@ def main():
         h.set_precision(0)
         extras["time_to_solution_s"] = {"fp64": elapsed / args.steps, "fp32_vcycle": inf32["seconds"]}
         extras["iterations"] = {"fp64": iters / args.steps, "fp32_vcycle": inf32["iterations"]}
+        if not args.no_learned:
+            # learned stage: a network trained on the GPU on plain-STMG pairs of an 8^3-cell box
+            # with the same mesh width, degrees and time step, then used on the full problem
+            from paper_2408_04372_amd import learned
+            tl = time.time()
+            theta, ch, losses = learned.train_for_config(args.config, solves=60, epochs=3, lr=2e-3, cells=8,
+                                                         log=log)
+            t_train = time.time() - tl
+            h.cnn_create(ch)
+            h.cnn_set_params(theta)
+            h.set_precision(2)
+            x.zero_()
+            h.solve(b, x)
+            x.zero_()
+            infl = h.solve(b, x)
+            h.set_precision(0)
+            extras["time_to_solution_s"]["learned"] = infl["seconds"]
+            extras["iterations"]["learned"] = infl["iterations"]
+            extras["learned"] = {"cnn_used": infl["cnn_used"], "cnn_fallbacks": infl["cnn_fallbacks"],
+                                 "rel_residual": infl["rel_residual"], "train_s": t_train,
+                                 "train_loss_first_last": [losses[0], losses[-1]], "channels": ch,
+                                 "train_solves": 60}
         # operator and V-cycle alone, event-timed
         for dt in (torch.float64, torch.float32):
             xv = torch.randn(nst, dtype=dt, device=dev)

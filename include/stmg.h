@@ -194,9 +194,14 @@ stmg_status stmg_set_precision(stmg_handle* h, int precision);
  *   tap = dx + 3 (dy + 3 dz), off = (dx - 1, dy - 1, dz - 1).
  * Parameters: one FP32 vector, per layer W (27 * C_out * C_in, tap, then C_out, then C_in)
  * followed by b (C_out).  Activations BF16, products on BF16 matrix cores with FP32
- * accumulation.  With precision STMG_PREC_LEARNED, stmg_solve uses
- *   z = C(r) + V(r - S C(r)), or z = V(r) when ||r - S C(r)|| >= ||r|| or C(r) is not finite
- * (V = FP32 V-cycle); info->cnn_used / cnn_fallbacks count the two cases. */
+ * accumulation.  With precision STMG_PREC_LEARNED, stmg_solve uses for an Arnoldi vector v
+ *   z = C(v) + V(v - S C(v))       (V = FP32 V-cycle)
+ * when plain multigrid accepts it, else z = V(v).  The stage is rejected when
+ * ||v - S C(v)|| >= ||v||, when C(v) is not finite, or when ||v - S z|| exceeds the value
+ * ||v' - S V(v')|| / ||v'|| of the last plain application (the first iteration of a solve
+ * is plain).  After three rejections in a row the network is not evaluated again in that
+ * solve.  info->cnn_used counts accepted stages, info->cnn_fallbacks the iterations that
+ * used the plain V-cycle. */
 
 /* Create (or replace) the network: n_layers in 1..6 convolutions, channels[0..n_layers]
  * with channels[0] = channels[n_layers] = n_t and every entry in 1..32.  Parameters start at 0. */

@@ -38,6 +38,16 @@ void ensure_workspace(stmg_handle* h, long long n, int m) {
 
 }  // namespace
 
+// ||v - w||_2 with w = S z already computed; tmp is overwritten
+static double stage_residual(stmg_handle* h, const double* v, const double* w, double* tmp, long long n) {
+  hipStream_t s = h->stream;
+  copy<double>(w, tmp, n, s);
+  axpby<double>(1.0, v, -1.0, tmp, n, s);
+  norm2_check<double>(tmp, n, h->dots.as<double>(), h->red.as<double>(), s);
+  std::vector<double> r = download<double>(h->dots.get(), 2, s);
+  return r[1] != 0.0 ? INFINITY : std::sqrt(r[0]);
+}
+
 stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = h->stream;
@@ -72,6 +82,10 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   stmg_status status = STMG_OK;
   int it = 0;
   double rel = 0.0;
+  // the learned stage is no longer evaluated in this solve after CNN_MAX_REJECT rejections in a row
+  constexpr int CNN_MAX_REJECT = 3;
+  int cnn_reject_run = 0;
+  double rho_plain = -1.0;     // ||v - S V(v)|| / ||v|| of the last plain preconditioner application
   if (bnorm == 0.0) {
     fill<double>(x, 0.0, n, s);
   } else {
@@ -103,24 +117,51 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
         h->timer.mark(TB_GMG, s);
         if (mixed) {
           float* z32 = h->Z32.as<float>() + (size_t)j * n;
-          if (learned) {
-            bool used = false;
-            cnn_precondition(h, vj, h->Z64.as<double>(), vn, &used);
-            if (used) inf.cnn_used++; else inf.cnn_fallbacks++;
-            cast_d2f(h->Z64.as<double>(), z32, n, s);
+          double* z64 = h->Z64.as<double>();
+          const bool judge = learned && cnn_reject_run < CNN_MAX_REJECT;
+          bool used = false;
+          if (judge && rho_plain >= 0.0) {
+            cnn_precondition(h, vj, z64, vn, &used);
+            cast_d2f(z64, z32, n, s);
           } else {
             cast_d2f(vj, h->tmp32a.as<float>(), n, s);
             vcycle<float>(h, 0, h->tmp32a.as<float>(), z32);
           }
-          cast_f2d(z32, h->Z64.as<double>(), n, s);
-          zj = h->Z64.as<double>();
+          cast_f2d(z32, z64, n, s);
+          zj = z64;
+          h->timer.mark(TB_OP, s);
+          vmult<double>(h, 0, zj, vn);
+          if (judge) {
+            // plain STMG judges the stage: accept it only if ||v_j - S z_j|| does not exceed
+            // what the last plain V-cycle reached (||v_j|| = 1); otherwise redo z_j = V(v_j)
+            h->timer.mark(TB_OTHER, s);
+            double rho = stage_residual(h, vj, vn, z64, n);
+            if (used && !(rho <= rho_plain)) {
+              used = false;
+              h->timer.mark(TB_GMG, s);
+              cast_d2f(vj, h->tmp32a.as<float>(), n, s);
+              vcycle<float>(h, 0, h->tmp32a.as<float>(), z32);
+              cast_f2d(z32, z64, n, s);
+              h->timer.mark(TB_OP, s);
+              vmult<double>(h, 0, z64, vn);
+              h->timer.mark(TB_OTHER, s);
+              rho = stage_residual(h, vj, vn, z64, n);
+              cnn_reject_run++;
+            } else if (used) {
+              cnn_reject_run = 0;
+            } else if (rho_plain >= 0.0) {
+              cnn_reject_run++;        // rejected by the network's own residual test
+            }
+            if (!used) rho_plain = rho;
+          }
+          if (learned) { if (used) inf.cnn_used++; else inf.cnn_fallbacks++; }
         } else {
           zj = h->Z64.as<double>() + (size_t)j * n;
           vcycle<double>(h, 0, vj, zj);
+          // w = S z_j
+          h->timer.mark(TB_OP, s);
+          vmult<double>(h, 0, zj, vn);
         }
-        // w = S z_j
-        h->timer.mark(TB_OP, s);
-        vmult<double>(h, 0, zj, vn);
         h->timer.mark(TB_OTHER, s);
         // classical Gram-Schmidt, two passes
         std::vector<double> hc(j + 1, 0.0);
