@@ -26,39 +26,78 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP64_MFMA_PEAK_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "st_apply3_heat3d_q4_dg2_c8_hbm_traffic.md")
+
+
+def code_hash(path):
+    """sha256 (16 hex digits) of a source file with // comments and blank lines removed."""
+    import hashlib
+    import re
+    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in open(path).read().splitlines()]
+    text = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def operator_traffic(cfg):
+    """HBM bytes per finest-level operator apply from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when the workload differs or the kernel source changed since it was measured."""
+    import hashlib
+    if cfg.name != "heat3d_32cube_Q4_perturbed_dG2_c8" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and line.split(":")[0].strip() in ("operator_traffic_bytes_per_apply",
+                                                          "operator_source_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    cur = code_hash(os.path.join(ROOT, "paper_2408_04372_amd", "csrc", "op_apply.hip"))
+    if vals.get("operator_source_sha256_16") != cur:
+        return None
+    return float(vals["operator_traffic_bytes_per_apply"])
+
+
 def kernel_roofline(h, cfg, ks, dtype_bytes=8):
-    """Algorithmic bytes/flops per launch of the finest-level operator and smoother kernels."""
+    """Algorithmic bytes and flops per launch (one apply = all colour dispatches) of the
+    finest-level operator and smoother kernels, and the resource that bounds each."""
     info = h.info
     n_t = info["n_t"]
     nx = info["n_x"][0]
     nst = n_t * nx
-    ncells = int(np.prod(cfg.n_cells[: cfg.dim]))
+    d = cfg.dim
+    ncells = int(np.prod(cfg.n_cells[:d]))
     n = cfg.p + 1
-    ns = n ** cfg.dim
+    ns = n ** d
     nt_cell = info["nt_cell"]
     c = n_t // nt_cell
-    meta = ncells * 8 + (int(np.prod([v + 1 for v in cfg.n_cells[: cfg.dim]])) * cfg.dim * 8
-                         if cfg.perturb else 0)
+    meta = ncells * 8 + (int(np.prod([v + 1 for v in cfg.n_cells[:d]])) * d * 8 if cfg.perturb else 0)
     out = {}
-    # operator kernel: y += S x  -> read x, read+write y, plus cell metadata
+    # operator: read x, read and write y, cell data; flops per (cell, temporal DoF): 12 sum-factorisation
+    # sweeps of n^(d+1) FMA, 10 FMA per quadrature point, temporal mixing at the n^d nodes
     op_bytes = 3 * nst * dtype_bytes + meta
-    # smoother kernel: u += omega sum_K ... -> read r, read+write u, read Q_K and the temporal inverses
+    op_flops = ncells * (n_t * (2 * 12 * n ** (d + 1) + 2 * 10 * n ** d) + 2 * info["temporal_nnz"] * n ** d)
+    # smoother: read r, read and write u, read Q_K and the temporal inverses; two GEMMs with Q_K
     asm_bytes = 3 * nst * dtype_bytes + ncells * (ns * ns + ns * nt_cell * nt_cell) * dtype_bytes
     asm_flops = ncells * (4 * ns * ns * n_t + 2 * ns * c * nt_cell * nt_cell)
-    if ks["n_operator"]:
-        t = ks["t_operator"] / ks["n_operator"]
-        out["operator"] = {"avg_s": t, "bytes": op_bytes, "GBs": op_bytes / t / 1e9}
-    if ks["n_smoother"]:
-        t = ks["t_smoother"] / ks["n_smoother"]
-        out["smoother"] = {"avg_s": t, "bytes": asm_bytes, "flops": asm_flops,
-                           "GBs": asm_bytes / t / 1e9, "TFLOPs": asm_flops / t / 1e12}
+    for key, nb, fl, peak_f, cnt, tt in (
+            ("operator", op_bytes, op_flops, FP64_VALU_PEAK_TFLOPS, ks["n_operator"], ks["t_operator"]),
+            ("smoother", asm_bytes, asm_flops, FP64_MFMA_PEAK_TFLOPS, ks["n_smoother"], ks["t_smoother"])):
+        if not cnt:
+            continue
+        t = tt / cnt
+        t_mem, t_fl = nb / (HBM_PEAK_GBS * 1e9), fl / (peak_f * 1e12)
+        out[key] = {"avg_s": t, "launches": cnt, "bytes": nb, "flops": fl, "GBs": nb / t / 1e9,
+                    "TFLOPs": fl / t / 1e12, "frac_hbm": nb / t / 1e9 / HBM_PEAK_GBS,
+                    "frac_flops": fl / t / 1e12 / peak_f,
+                    "bound": ("alu" if key == "operator" else "mfma") if t_fl > t_mem else "hbm",
+                    "speed_of_light_s": max(t_mem, t_fl)}
     return out
 
 
@@ -175,13 +214,18 @@ def main():
             f"other {inf['t_other']:.3f}")
     value = nst * iters / elapsed
     kr = kernel_roofline(h, cfg, ks)
-    dominant = max(kr, key=lambda k: kr[k]["avg_s"] * (ks["n_smoother"] if k == "smoother" else ks["n_operator"]))
+    dominant = max(kr, key=lambda k: kr[k]["avg_s"] * kr[k]["launches"])
     d = kr[dominant]
-    roofline = {"kernel": "smoother (k_asm_apply, finest level)" if dominant == "smoother"
-                else "operator (st_apply3, finest level)",
-                "bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_s": d["avg_s"], "bytes_per_launch": d["bytes"]}
+    if d["bound"] == "hbm":
+        ach, peak, unit, frac = d["GBs"], HBM_PEAK_GBS, "GB/s", d["frac_hbm"]
+    else:
+        ach, peak, unit, frac = d["TFLOPs"], FP64_VALU_PEAK_TFLOPS, "TFLOP/s", d["frac_flops"]
+    roofline = {"kernel": "smoother (k_asm_mfma, finest level, 8 colour dispatches)" if dominant == "smoother"
+                else "operator (st_apply3, finest level, 8 colour dispatches)",
+                "bound": d["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": frac,
+                "traffic": operator_traffic(cfg) if dominant == "operator" else None,
+                "avg_launch_s": d["avg_s"], "bytes_per_launch": d["bytes"], "flops_per_launch": d["flops"],
+                "frac_hbm": d["frac_hbm"], "frac_flops": d["frac_flops"]}
     extras = {"kernels": kr, "kernel_counts": ks}
     if not args.no_extras:
         # time to 1e-8 with the FP32 V-cycle inside FP64 FGMRES

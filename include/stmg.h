@@ -8,16 +8,16 @@
  *   - spatial continuous Q_p on a structured hexahedral (d = 3) or
  *     quadrilateral (d = 2) mesh of [lo, hi], Cartesian or with displaced
  *     vertices (multilinear cells), homogeneous Dirichlet data on the boundary
- *     (Section 2, eqs. fespace and space-matrices);
+ *     (Sections 1.1 and 2, eqs. fespace and space-matrices);
  *   - dG(k) or cGP(k) in time, c time cells batched into one slab
- *     (Sections 3.1-3.2, eqs. heat-cg-dg-at-once, wave-cg-dg-at-once,
+ *     (Sections 2.1-2.2, eqs. heat-cg-dg-at-once, wave-cg-dg-at-once,
  *     heat-cg-cg-at-once, wave-cg-cg-at-once).  For every pair the slab matrix
  *     is S = M_T (x) A_h + N_T (x) M_h with small dense temporal factors M_T, N_T
  *     (N_T = A_T for heat, A_T M_T^{-1} A_T for the condensed wave system);
  *   - solver: flexible GMRES in FP64, preconditioned by one space-time multigrid
- *     V-cycle per iteration (Section 4, Alg. stmg) with the space-time cell-wise
+ *     V-cycle per iteration (Section 3, Alg. stmg) with the space-time cell-wise
  *     additive Schwarz smoother (eqs. vanka0 and vanka) and spatial h/p transfers
- *     (Section 4.2, Alg. mg-sequence, spatial levels only).
+ *     (Section 3.2, Alg. mg-sequence, spatial levels only).
  *
  * Vector layout (every device vector argument): time-major [n_t][N_x], where
  * N_x = prod_d (p * n_cells[d] + 1) lattice nodes ordered x fastest, n_t =
@@ -111,7 +111,7 @@ typedef struct {
   int32_t n_levels;
   int32_t n_t;
   int32_t nt_cell;                          /* temporal DoFs per time cell */
-  int32_t reserved0;
+  int32_t temporal_nnz;                     /* nonzeros of M_T plus nonzeros of N_T */
   int64_t n_x[STMG_MAX_LEVELS];             /* lattice nodes per level */
   int32_t p[STMG_MAX_LEVELS];
   int32_t cells[STMG_MAX_LEVELS][3];
@@ -124,7 +124,7 @@ typedef struct {
 typedef struct stmg_handle stmg_handle;
 
 /* Build the level hierarchy, smoother factors, relaxation parameters and the
- * coarse-level inverse (Section 4; Alg. mg-sequence with spatial levels).
+ * coarse-level inverse (Section 3; Alg. mg-sequence with spatial levels).
  * vertices: host, nullable.  NULL means a Cartesian box [lo, hi]; otherwise
  *   (n_cells+1)^dim vertex positions, x fastest, dim doubles each.  Cells must
  *   not be inverted (STMG_E_ARG otherwise).
@@ -150,17 +150,17 @@ stmg_status stmg_smooth(stmg_handle* h, int level, int dtype, const void* b, voi
  * guess, nu1 = nu2 = n_smooth, exact coarsest-level solve.  r, z must not alias. */
 stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z);
 
-/* fine = P coarse: prolongation from level+1 to level (Section 4.2): the coarse
+/* fine = P coarse: prolongation from level+1 to level (Section 3.2): the coarse
  * Q_p function evaluated at the fine nodes; Dirichlet values of coarse are
  * treated as zero and fine Dirichlet values are written as zero. */
 stmg_status stmg_prolongate(stmg_handle* h, int level, int dtype, const void* coarse, void* fine);
 
-/* coarse = P^T fine (Section 4.2, restriction = adjoint of prolongation) on
+/* coarse = P^T fine (Section 3.2, restriction = adjoint of prolongation) on
  * interior nodes; coarse Dirichlet values are written as zero. */
 stmg_status stmg_restrict(stmg_handle* h, int level, int dtype, const void* fine, void* coarse);
 
 /* Solve S x = b with FP64 flexible GMRES(restart) right-preconditioned by one
- * V-cycle per iteration (Section 5 solver set-up; precision selects an FP64,
+ * V-cycle per iteration (Section 4 solver set-up; precision selects an FP64,
  * FP32 or learned+FP32 preconditioner).  b, x: device double vectors; x holds
  * the initial guess on entry.  Dirichlet entries of b and x are set to zero
  * (homogeneous data).  Returns STMG_E_NOCONV (with info filled) if rtol is

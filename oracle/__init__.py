@@ -9,12 +9,12 @@ and by the ``cpu_baseline`` leg of ``bench.py``.
 Modules
   basis      1D quadrature rules and Lagrange bases (Section 2, Q_p space; Appendix-style node sets)
   temporal   dG(k) and cGP(k) time matrices and slab-level Kronecker factors
-             (Sections 3.1 and 3.2, eqs. dg-time-weights, cg-time-weights)
+             (Sections 2.1 and 2.2, eqs. dg-time-weights, cg-time-weights)
   spatial    meshes, cell matrices by quadrature, assembled M_h and A_h (eq. space-matrices)
   spacetime  the all-at-once slab operator (eqs. heat-cg-dg-at-once ... wave-cg-cg-at-once)
   rhs        slab right-hand sides and velocity recovery
-  mg         transfers, cell-wise additive Schwarz smoother, V-cycle (Section 4, Alg. stmg)
-  krylov     flexible GMRES with a V-cycle preconditioner (Section 5 solver setup)
+  mg         transfers, cell-wise additive Schwarz smoother, V-cycle (Section 3, Alg. stmg)
+  krylov     flexible GMRES with a V-cycle preconditioner (Section 4 solver setup)
   norms      L2(L2) errors and wave energy
   cnn        FP64 reference of the learned preconditioning stage (not in the paper: parity unpinned)
 """

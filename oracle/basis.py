@@ -1,10 +1,10 @@
 """1D node sets, quadrature rules and Lagrange bases on the reference interval [0, 1].
 
 Section 2 defines Q_p through a nodal Lagrange basis without naming the nodes;
-the reading used here is Gauss-Lobatto-Legendre (GLL) nodes.  Section 3.1 puts
+the reading used here is Gauss-Lobatto-Legendre (GLL) nodes.  Section 2.1 puts
 the dG(k) temporal basis at the k+1 Gauss-Radau points (right-sided: the last
 node is t = 1, which the slab coupling through the previous end value needs);
-Section 3.2 puts the cGP(k) trial basis at the k+1 Gauss-Lobatto points.
+Section 2.2 puts the cGP(k) trial basis at the k+1 Gauss-Lobatto points.
 """
 from __future__ import annotations
 

@@ -1,4 +1,4 @@
-"""Flexible GMRES(m) with right preconditioning (Section 5: GMRES, one V-cycle per iteration).
+"""Flexible GMRES(m) with right preconditioning (Section 4: GMRES, one V-cycle per iteration).
 
 Plain textbook FGMRES: modified Gram-Schmidt Arnoldi, Givens rotations, the
 update x = x0 + Z y at restart, and a true-residual check at each restart.

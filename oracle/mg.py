@@ -1,11 +1,11 @@
 """Space-time multigrid: hierarchy, transfers, cell-wise additive Schwarz, V-cycle.
 
-Section 4 of the paper.  Readings where the paper is silent:
+Section 3 of the paper.  Readings where the paper is silent:
   * hierarchy (Alg. mg-sequence, spatial levels only): halve p while p > min_p
     (4 -> 2 -> 1, 3 -> 1, 2 -> 1), then halve the cell count per direction while
     it stays even and >= 2 * coarse_cells; coarse h-levels use the even-index
     vertex subset and re-discretise (coefficient lookup in spatial.Space).
-  * transfers (Section 4.2): prolongation evaluates the coarse Q_p function at
+  * transfers (Section 3.2): prolongation evaluates the coarse Q_p function at
     the fine nodes through the fine node's reference coordinates in its coarse
     parent cell (the L2 embedding of nested spaces); restriction is the exact
     transpose.  Both act on interior nodes only (Dirichlet rows/columns dropped).

@@ -1,4 +1,4 @@
-"""Slab right-hand sides and velocity recovery (Sections 3.1-3.2).
+"""Slab right-hand sides and velocity recovery (Sections 2.1-2.2).
 
 Loads F^i = (f(., t_i), phi) at the temporal DoF times are integrated in space
 with (p+2)-point Gauss rules.  The printed load term "M_tau (x) M_h f" counts

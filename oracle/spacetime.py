@@ -1,6 +1,6 @@
 """The all-at-once slab operator S = M_T (x) A_h + N_T (x) M_h (eq. lin-sys).
 
-Sections 3.1-3.2 give the four slab systems (eqs. heat-cg-dg-at-once,
+Sections 2.1-2.2 give the four slab systems (eqs. heat-cg-dg-at-once,
 wave-cg-dg-at-once, heat-cg-cg-at-once, wave-cg-cg-at-once); temporal.slab
 writes each as one Kronecker sum.  Vectors are full-lattice space-time vectors
 of shape (n_t, N_x): row i is the spatial vector of temporal DoF i (the block

@@ -1,18 +1,18 @@
 """Spatial Q_p finite elements on structured hexahedral (or quadrilateral) meshes.
 
-Section 2 (eqs. fespace, space-matrices): continuous Q_p on cells given by a
+Sections 1.1 and 2 (eqs. fespace, space-matrices): continuous Q_p on cells given by a
 reference mapping, nodal Lagrange basis, M_h = (phi_i, phi_j) and
 A_h = (rho grad phi_i, grad phi_j).  Readings used where the paper is silent:
 GLL nodes per direction, (p+1)-point Gauss quadrature per direction, bilinear /
 trilinear cells built from the vertex lattice, homogeneous Dirichlet data on
-the whole boundary (Section 5.1).
+the whole boundary (Section 4.1).
 
 Lattice conventions: cell index c = cx + nx*(cy + ny*cz); node index
 g = gx + Nx*(gy + Ny*gz) with N = p*n + 1 per direction; cell-local node
 a = lx + (p+1)*(ly + (p+1)*lz).
 
 Coefficients on coarse multigrid levels (geometric MG re-discretisation,
-Section 4): at a quadrature point with reference coordinate xi in a cell that
+Section 3): at a quadrature point with reference coordinate xi in a cell that
 covers r^d finest cells, the coefficient is that of the finest descendant cell
 whose reference sub-box contains xi (for Cartesian meshes this is the finest
 cell that contains the physical point).

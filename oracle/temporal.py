@@ -1,6 +1,6 @@
 """Temporal matrices of dG(k) and cGP(k) and their slab-level Kronecker factors.
 
-dG(k), Section 3.1 (eq. dg-time-weights).  Trial = test = P_k on each time cell
+dG(k), Section 2.1 (eq. dg-time-weights).  Trial = test = P_k on each time cell
 with the Lagrange basis at the k+1 right Gauss-Radau points.  The printed
 derivative matrix and alpha are garbled; the reading used here comes from the
 upwind jump term of eq. var-heat-dg:
@@ -8,11 +8,11 @@ upwind jump term of eq. var-heat-dg:
     (A_tau)_ij = int_0^1 xi_j' xi_i + xi_j(0) xi_i(0),
     alpha_i    = xi_i(0)   (couples the previous cell's value at its end, the last DoF).
 
-cGP(k), Section 3.2 (eq. cg-time-weights).  Trial P_k at the k+1 Gauss-Lobatto
+cGP(k), Section 2.2 (eq. cg-time-weights).  Trial P_k at the k+1 Gauss-Lobatto
 points, test P_{k-1} at the last k of them.  The first trial DoF is fixed by
 continuity; its weights are beta (mass) and alpha (derivative).
 
-Slab level (Sections 3.1-3.2, the all-at-once systems): c time cells give
+Slab level (Sections 2.1-2.2, the all-at-once systems): c time cells give
 block lower-bidiagonal temporal factors M_T, A_T.  In every case the slab
 operator is S = M_T (x) A_h + N_T (x) M_h with N_T = A_T (heat) or
 N_T = A_T M_T^{-1} A_T (wave, after eliminating the velocity).  For the wave

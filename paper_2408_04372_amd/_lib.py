@@ -58,7 +58,7 @@ class SolveInfo(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [
         ("n_levels", ctypes.c_int32), ("n_t", ctypes.c_int32), ("nt_cell", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("temporal_nnz", ctypes.c_int32),
         ("n_x", ctypes.c_int64 * MAX_LEVELS), ("p", ctypes.c_int32 * MAX_LEVELS),
         ("cells", (ctypes.c_int32 * 3) * MAX_LEVELS), ("omega", ctypes.c_double * MAX_LEVELS),
         ("coarse_unknowns", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
@@ -202,7 +202,7 @@ class Handle:
         inf = Info()
         _check(self.lib.stmg_query(self.h, ctypes.byref(inf)))
         L = inf.n_levels
-        return {"n_levels": L, "n_t": inf.n_t, "nt_cell": inf.nt_cell,
+        return {"n_levels": L, "n_t": inf.n_t, "nt_cell": inf.nt_cell, "temporal_nnz": inf.temporal_nnz,
                 "n_x": [inf.n_x[i] for i in range(L)], "p": [inf.p[i] for i in range(L)],
                 "cells": [tuple(inf.cells[i][:]) for i in range(L)],
                 "omega": [inf.omega[i] for i in range(L)], "coarse_unknowns": inf.coarse_unknowns,

@@ -330,6 +330,11 @@ stmg_status stmg_query(stmg_handle* h, stmg_info* info) {
     info->n_levels = (int)h->levels.size();
     info->n_t = h->tm.n_t;
     info->nt_cell = h->tm.nt_cell;
+    int nnz = 0;
+    for (const stmg::hm::Mat* A : {&h->tm.M_T, &h->tm.N_T})
+      for (int i = 0; i < A->r; ++i)
+        for (int j = 0; j < A->c; ++j) nnz += ((*A)(i, j) != 0.0);
+    info->temporal_nnz = nnz;
     for (size_t l = 0; l < h->levels.size(); ++l) {
       const stmg::Level& L = *h->levels[l];
       info->n_x[l] = L.g.nx;

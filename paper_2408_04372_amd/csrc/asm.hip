@@ -1,4 +1,4 @@
-// Space-time cell-wise additive Schwarz smoother (Section 4.3, eqs. vanka0, vanka).
+// Space-time cell-wise additive Schwarz smoother (Section 3.3, eqs. vanka0, vanka).
 //
 // The block of space-time cell K x I_m is the principal submatrix of the level
 // operator on K's interior nodes and I_m's temporal DoFs.  Because the slab

@@ -1,4 +1,4 @@
-// The library handle: level hierarchy (Section 4, Alg. mg-sequence with spatial
+// The library handle: level hierarchy (Section 3, Alg. mg-sequence with spatial
 // levels), per-precision V-cycle data, and the FP64 FGMRES workspace.
 #pragma once
 

@@ -1,5 +1,5 @@
 // Level hierarchy, smoother set-up, relaxation estimates and the V-cycle
-// (Section 4: Alg. stmg and Alg. mg-sequence, spatial levels only).
+// (Section 3: Alg. stmg and Alg. mg-sequence, spatial levels only).
 //
 // Level sequence (finest first): halve p while p > min_p, then halve the cell
 // count per direction while every direction stays even and does not drop below

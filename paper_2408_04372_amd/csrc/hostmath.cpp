@@ -2,8 +2,8 @@
 //
 // Node sets are computed from Legendre polynomials by bracketing sign changes
 // on a fine grid and bisection, which is robust for the small degrees used here.
-// Temporal matrices follow Sections 3.1 (dG, right Radau basis, upwind jump) and
-// 3.2 (cGP, Gauss-Lobatto trial / last-k test basis), integrated exactly with a
+// Temporal matrices follow Sections 2.1 (dG, right Radau basis, upwind jump) and
+// 2.2 (cGP, Gauss-Lobatto trial / last-k test basis), integrated exactly with a
 // Gauss rule of sufficient order.
 #include "hostmath.hpp"
 

@@ -31,7 +31,7 @@ Vec gauss_radau_right(int n);
 // Lagrange basis on `nodes`: val[q][i] = l_i(x_q), der[q][i] = l_i'(x_q).
 void lagrange(const Vec& nodes, const Vec& x, Mat& val, Mat& der);
 
-// Slab-level temporal data (Sections 3.1-3.2).
+// Slab-level temporal data (Sections 2.1-2.2).
 struct Temporal {
   int n_t = 0, nt_cell = 0, c = 0;
   Mat M_T, A_T, N_T;      // n_t x n_t

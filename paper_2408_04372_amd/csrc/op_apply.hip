@@ -1,5 +1,5 @@
 // Matrix-free space-time operator  y += scale * (M_T (x) A_h + N_T (x) M_h) x  on
-// interior rows (Section 4.1: S = sum_c P_c^T B_c^T D_c B_c P_c with sum
+// interior rows (Section 3.1: S = sum_c P_c^T B_c^T D_c B_c P_c with sum
 // factorisation; the temporal factors are small dense matrices and A_h u^i,
 // M_h u^i are formed once per temporal DoF and reused).
 //

@@ -1,5 +1,5 @@
 // FP64 flexible GMRES(m) preconditioned by one space-time multigrid V-cycle per
-// iteration (Section 5: GMRES with one V-cycle per iteration).  Right
+// iteration (Section 4: GMRES with one V-cycle per iteration).  Right
 // preconditioning; classical Gram-Schmidt applied twice (two fused multi-dot /
 // multi-axpy passes per Arnoldi step); Givens rotations and the small least-
 // squares problem on the host.  The residual, the Krylov basis and the solution

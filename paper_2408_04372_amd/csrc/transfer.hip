@@ -1,4 +1,4 @@
-// Spatial grid transfers (Section 4.2).  On the structured lattice the
+// Spatial grid transfers (Section 3.2).  On the structured lattice the
 // prolongation is a Kronecker product of 1D interpolation matrices
 // (P = P_z (x) P_y (x) P_x, applied to every temporal plane, "P^h (x) u"), so it is
 // applied as d one-dimensional sweeps; the restriction R = P^T uses the transposed

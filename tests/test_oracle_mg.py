@@ -1,4 +1,4 @@
-"""Pins of the oracle's multigrid parts (Section 4: transfers, ASM smoother, V-cycle)."""
+"""Pins of the oracle's multigrid parts (Section 3: transfers, ASM smoother, V-cycle)."""
 import numpy as np
 import pytest
 
@@ -67,7 +67,7 @@ def test_asm_single_cell_is_exact(method, problem):
 
 
 def test_asm_block_sizes():
-    # block size (k+1)(p+1)^d for dG(k) and k(p+1)^d for cGP(k) on interior cells (Section 4.3)
+    # block size (k+1)(p+1)^d for dG(k) and k(p+1)^d for cGP(k) on interior cells (Section 3.3)
     for method, k, per in [(0, 2, 3), (1, 2, 2)]:
         cfg = Config(dim=3, time_method=method, k=k, p=2, n_time_cells=2, n_cells=(3, 3, 3), tau=0.1)
         op = _op(cfg)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's slab operator and right-hand sides (Sections 3.1-3.2, 5.1)."""
+"""Pins of the oracle's slab operator and right-hand sides (Sections 2.1-2.2, 5.1)."""
 import json
 import os
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's temporal matrices (Sections 3.1-3.2) against closed forms."""
+"""Pins of the oracle's temporal matrices (Sections 2.1-2.2) against closed forms."""
 import math
 
 import numpy as np
