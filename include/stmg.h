@@ -88,7 +88,8 @@ typedef struct {
   int32_t precision;       /* stmg_precision: preconditioner used by stmg_solve */
   int32_t restart;         /* FGMRES restart length m >= 1 */
   int32_t max_iter;        /* total FGMRES iterations allowed */
-  int32_t reserved0;
+  int32_t gram_schmidt;    /* 0: one classical Gram-Schmidt pass, a second one only when the first
+                              removes more than 7/8 of ||w||; 1: always two passes */
   double rtol;             /* stop at ||b - S x||_2 / ||b||_2 <= rtol (true residual) */
   uint64_t seed;           /* reserved for randomised setup steps */
 } stmg_config;

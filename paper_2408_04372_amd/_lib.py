@@ -38,7 +38,7 @@ class CConfig(ctypes.Structure):
         ("n_smooth", ctypes.c_int32), ("min_p", ctypes.c_int32), ("coarse_cells", ctypes.c_int32),
         ("vcycle_dtypes", ctypes.c_int32), ("omega", ctypes.c_double),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32), ("rtol", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("gram_schmidt", ctypes.c_int32), ("rtol", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -149,6 +149,7 @@ def c_config(cfg, **overrides) -> CConfig:
     c.lo[:] = [float(v) for v in (list(get("lo")) + [0, 0, 0])[:3]]
     c.hi[:] = [float(v) for v in (list(get("hi")) + [1, 1, 1])[:3]]
     c.vcycle_dtypes = int(overrides.get("vcycle_dtypes", 0))
+    c.gram_schmidt = int(overrides.get("gram_schmidt", 0))
     c.omega = float(get("omega"))
     c.rtol = float(get("rtol"))
     c.seed = int(get("seed"))

@@ -53,6 +53,7 @@ void check_config(const stmg_config* c) {
   if (c->coarse_cells < 1) fail(STMG_E_ARG, "coarse_cells must be >= 1");
   if (c->precision < 0 || c->precision > 2) fail(STMG_E_ARG, "precision must be 0, 1 or 2");
   if (c->restart < 1 || c->restart > 200) fail(STMG_E_ARG, "restart must be in 1..200");
+  if (c->gram_schmidt != 0 && c->gram_schmidt != 1) fail(STMG_E_ARG, "gram_schmidt must be 0 or 1");
   if (c->max_iter < 1) fail(STMG_E_ARG, "max_iter must be >= 1");
   if (!(c->rtol > 0.0)) fail(STMG_E_ARG, "rtol must be positive");
   if (c->vcycle_dtypes < 0 || c->vcycle_dtypes > 3) fail(STMG_E_ARG, "vcycle_dtypes must be in 0..3");

@@ -63,20 +63,26 @@ __device__ inline double block_sum(double v, double* sh) {
 
 // partial dots of up to JC vectors against w: part[block * JC + j]
 __global__ void k_dot_part(const double* __restrict__ V, long long ldv, int kc,
-                           const double* __restrict__ w, long long n, double* __restrict__ part) {
+                           const double* __restrict__ w, long long n, double* __restrict__ part, int self) {
   __shared__ double sh[BS / 64];
   double acc[JC];
+  double ww = 0.0;
 #pragma unroll
   for (int j = 0; j < JC; ++j) acc[j] = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     double wi = w[i];
+    ww += wi * wi;
 #pragma unroll
     for (int j = 0; j < JC; ++j)
       if (j < kc) acc[j] += V[j * ldv + i] * wi;
   }
   for (int j = 0; j < kc; ++j) {
     double s = block_sum(acc[j], sh);
-    if (threadIdx.x == 0) part[blockIdx.x * JC + j] = s;
+    if (threadIdx.x == 0) part[blockIdx.x * PS + j] = s;
+  }
+  if (self) {
+    double s = block_sum(ww, sh);
+    if (threadIdx.x == 0) part[blockIdx.x * PS + kc] = s;
   }
 }
 
@@ -84,7 +90,7 @@ __global__ void k_dot_final(const double* __restrict__ part, int nblocks, int kc
   __shared__ double sh[BS / 64];
   int j = blockIdx.x;
   double v = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[b * JC + j];
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[b * PS + j];
   double s = block_sum(v, sh);
   if (threadIdx.x == 0) out[j] = s;
 }
@@ -96,6 +102,24 @@ __global__ void k_multi_axpy_neg(const double* __restrict__ V, long long ldv, in
     for (int j = 0; j < k; ++j) s -= h[j] * V[j * ldv + i];
     w[i] = s;
   }
+}
+
+// the update above fused with the partial sums of the new ||w||^2 and a non-finite flag
+__global__ void k_multi_axpy_neg_norm(const double* __restrict__ V, long long ldv, int k,
+                                      const double* __restrict__ h, double* __restrict__ w, long long n,
+                                      double* __restrict__ part) {
+  __shared__ double sh[BS / 64];
+  double acc = 0.0, bad = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double s = w[i];
+    for (int j = 0; j < k; ++j) s -= h[j] * V[j * ldv + i];
+    w[i] = s;
+    if (!isfinite(s)) bad = 1.0;
+    else acc += s * s;
+  }
+  double a = block_sum(acc, sh);
+  double b = block_sum(bad, sh);
+  if (threadIdx.x == 0) { part[blockIdx.x * PS] = a; part[blockIdx.x * PS + 1] = b; }
 }
 
 template <class T>
@@ -119,7 +143,7 @@ __global__ void k_norm_part(const T* __restrict__ x, long long n, double* part) 
   }
   double s = block_sum(acc, sh);
   double b = block_sum(bad, sh);
-  if (threadIdx.x == 0) { part[blockIdx.x * JC] = s; part[blockIdx.x * JC + 1] = b; }
+  if (threadIdx.x == 0) { part[blockIdx.x * PS] = s; part[blockIdx.x * PS + 1] = b; }
 }
 
 }  // namespace
@@ -168,14 +192,15 @@ void boundary_axpby(const int* bidx, long long nb, long long nx, int n_t, T a, c
 }
 
 void multi_dot(const double* V, long long ldv, int k, const double* w, long long n, double* out,
-               double* part, hipStream_t s) {
+               double* part, hipStream_t s, bool self) {
   unsigned nb = grid_for(n);
   if (nb > RED_BLOCKS) nb = RED_BLOCKS;
   for (int j0 = 0; j0 < k; j0 += JC) {
     int kc = k - j0 < JC ? k - j0 : JC;
-    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(BS), 0, s, V + j0 * ldv, ldv, kc, w, n, part);
+    int sf = (self && j0 + kc == k) ? 1 : 0;     // w . w with the last group, into out[k]
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(BS), 0, s, V + j0 * ldv, ldv, kc, w, n, part, sf);
     STMG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_dot_final, dim3(kc), dim3(BS), 0, s, part, (int)nb, kc, out + j0);
+    hipLaunchKernelGGL(k_dot_final, dim3(kc + sf), dim3(BS), 0, s, part, (int)nb, kc + sf, out + j0);
     STMG_CHECK_LAUNCH();
   }
 }
@@ -184,6 +209,16 @@ void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, doub
                     hipStream_t s) {
   if (n <= 0 || k <= 0) return;
   hipLaunchKernelGGL(k_multi_axpy_neg, dim3(grid_for(n)), dim3(BS), 0, s, V, ldv, k, h, w, n);
+  STMG_CHECK_LAUNCH();
+}
+
+void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h, double* w, long long n,
+                         double* out, double* part, hipStream_t s) {
+  unsigned nb = grid_for(n);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  hipLaunchKernelGGL(k_multi_axpy_neg_norm, dim3(nb), dim3(BS), 0, s, V, ldv, k, h, w, n, part);
+  STMG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_dot_final, dim3(2), dim3(BS), 0, s, part, (int)nb, 2, out);
   STMG_CHECK_LAUNCH();
 }
 

@@ -364,7 +364,7 @@ void cnn_create(stmg_handle* h, int n_layers, const int* channels) {
   c->m.alloc(sizeof(float) * off);
   c->v.alloc(sizeof(float) * off);
   c->grad.alloc(sizeof(float) * off);
-  c->red.alloc(sizeof(double) * RED_BLOCKS * JC);
+  c->red.alloc(sizeof(double) * RED_BLOCKS * PS);
   c->lossbuf.alloc(sizeof(double) * 4);
   int cpmax = 16;
   for (int l = 0; l <= n_layers; ++l) cpmax = std::max(cpmax, c->cp[l]);

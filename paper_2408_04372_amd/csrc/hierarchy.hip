@@ -650,7 +650,7 @@ void estimate_omegas(stmg_handle* h) {
   hipStream_t s = h->stream;
   const int steps = 15;
   int n_t = h->tm.n_t;
-  DevBuf red(sizeof(double) * RED_BLOCKS * JC), dots(sizeof(double) * 64);
+  DevBuf red(sizeof(double) * RED_BLOCKS * PS), dots(sizeof(double) * 64);
   for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
     Level& L = *h->levels[l];
     long long n = L.nst(n_t);

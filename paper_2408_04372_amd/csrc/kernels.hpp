@@ -35,15 +35,20 @@ void cast_f2d(const float* x, double* y, long long n, hipStream_t s);
 template <class T>
 void boundary_axpby(const int* bidx, long long nb, long long nx, int n_t, T a, const T* x, T c, T* y,
                     hipStream_t s);
-// Reduction workspace: RED_BLOCKS * JC doubles of device memory.
+// Reduction workspace: RED_BLOCKS * PS doubles of device memory (JC vectors per pass plus one).
 constexpr int RED_BLOCKS = 1024;
-constexpr int JC = 8;
+constexpr int JC = 32;
+constexpr int PS = JC + 1;
 // out[j] = sum_i V_j[i] * w[i] for j < k (V_j = V + j * ldv), double accumulation; out on device.
+// With self = true also out[k] = w . w.  Vectors are read once per group of JC.
 void multi_dot(const double* V, long long ldv, int k, const double* w, long long n, double* out,
-               double* ws, hipStream_t s);
+               double* ws, hipStream_t s, bool self = false);
 // w -= sum_j h[j] V_j  (h on device)
 void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, double* w, long long n,
                     hipStream_t s);
+// w -= sum_j h[j] V_j, then out[0] = w . w and out[1] = 1 if w holds NaN/Inf (else 0)
+void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h, double* w, long long n,
+                         double* out, double* ws, hipStream_t s);
 // x += sum_j y[j] Z_j  (y on device, Z in T)
 template <class T>
 void multi_axpy_acc(const T* Z, long long ldz, int k, const double* y, double* x, long long n,

@@ -23,7 +23,7 @@ void ensure_workspace(stmg_handle* h, long long n, int m) {
   if (h->krylov_m == m && h->V.get()) return;
   h->V.alloc(sizeof(double) * n * (m + 1));
   h->w.alloc(sizeof(double) * n);
-  h->red.alloc(sizeof(double) * RED_BLOCKS * JC);
+  h->red.alloc(sizeof(double) * RED_BLOCKS * PS);
   h->dots.alloc(sizeof(double) * (m + 2));
   if (need32) {
     h->Z32.alloc(sizeof(float) * n * m);
@@ -84,6 +84,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   double rel = 0.0;
   // the learned stage is no longer evaluated in this solve after CNN_MAX_REJECT rejections in a row
   constexpr int CNN_MAX_REJECT = 3;
+  constexpr double GS_REFINE = 0.125;
   int cnn_reject_run = 0;
   double rho_plain = -1.0;     // ||v - S V(v)|| / ||v|| of the last plain preconditioner application
   if (bnorm == 0.0) {
@@ -163,17 +164,22 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
           vmult<double>(h, 0, zj, vn);
         }
         h->timer.mark(TB_OTHER, s);
-        // classical Gram-Schmidt, two passes
+        // classical Gram-Schmidt: one pass reads V once for V^T w and ||w||^2, one fused pass
+        // updates w and returns ||w'||^2; a second pass follows when the pass cancelled most of
+        // w (||w'|| < GS_REFINE ||w||) or when two passes are requested
         std::vector<double> hc(j + 1, 0.0);
+        std::vector<double> w2;
         for (int pass = 0; pass < 2; ++pass) {
-          multi_dot(V, n, j + 1, vn, n, dots, red, s);
-          std::vector<double> hv = download<double>(dots, j + 1, s);
-          multi_axpy_neg(V, n, j + 1, dots, vn, n, s);
+          multi_dot(V, n, j + 1, vn, n, dots, red, s, true);
+          std::vector<double> hv = download<double>(dots, j + 2, s);
+          multi_axpy_neg_norm(V, n, j + 1, dots, vn, n, dots, red, s);
+          w2 = download<double>(dots, 2, s);
           for (int i = 0; i <= j; ++i) hc[i] += hv[i];
+          const double ww = hv[j + 1];
+          if (!std::isfinite(ww) || w2[1] != 0.0) { bad = true; break; }
+          if (h->cfg.gram_schmidt == 0 && w2[0] >= GS_REFINE * GS_REFINE * ww) break;
         }
-        norm2_check<double>(vn, n, dots, red, s);
-        std::vector<double> w2 = download<double>(dots, 2, s);
-        if (w2[1] != 0.0) { bad = true; break; }
+        if (bad) break;
         double hn = std::sqrt(w2[0]);
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
         H[(size_t)(j + 1) * m + j] = hn;

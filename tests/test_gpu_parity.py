@@ -135,14 +135,15 @@ def test_omega_estimate(name, rule):
     assert np.allclose(got, ref, rtol=1e-4)
 
 
-@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2",
-                                  "heat2d_q4_cgp2_pert", "wave3d_q2_cgp1_ragged"])
-def test_solve_fp64_matches_direct(name):
+@pytest.mark.parametrize("name,gs", [("heat2d_q2_dg1", 0), ("heat3d_q2_dg1_pert", 0), ("wave3d_q3_cgp2", 0),
+                                     ("heat2d_q4_cgp2_pert", 0), ("wave3d_q2_cgp1_ragged", 0),
+                                     ("heat3d_q2_dg1_pert", 1), ("wave3d_q3_cgp2", 1)])
+def test_solve_fp64_matches_direct(name, gs):
     cfg, verts, coef = problem(name)
     op = oracle_op(cfg, verts, coef)
     b = si.random_slab_vector(cfg, 11)
     xd = op.solve(b)
-    with _handle(cfg, verts, coef, rtol=1e-12, precision=0, max_iter=300) as h:
+    with _handle(cfg, verts, coef, rtol=1e-12, precision=0, max_iter=300, gram_schmidt=gs) as h:
         x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
         info = h.solve(_t(b).view(-1), x)
         err = np.linalg.norm(_np(x) - xd.ravel()) / np.linalg.norm(xd)
