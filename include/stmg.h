@@ -186,6 +186,15 @@ stmg_status stmg_kernel_stats_get(stmg_handle* h, stmg_kernel_stats* out, int re
  * V-cycle data must have been built (vcycle_dtypes). */
 stmg_status stmg_set_precision(stmg_handle* h, int precision);
 
+/* Velocity of the wave slab from its displacement (Sections 2.1.2 and 2.2.2, eqs.
+ * wave-cg-dg-ade and wave-cg-cg-ade; the second equation of the first-order system):
+ *   dG(k):  V = M_T^{-1} (A_T U - a u0),    cGP(k): V = M_T^{-1} (A_T U + a u0 - b v0),
+ * a = e_1 (x) alpha, b = e_1 (x) beta (first time cell only).  U, V: device FP64 [n_t][N_x]
+ * on the finest level; u0, v0: device FP64 [N_x] initial displacement and velocity of the
+ * slab (NULL reads as zero; v0 is not used by dG).  Asynchronous on the handle's stream.
+ * STMG_E_UNSUPPORTED for the heat problem; STMG_E_ARG for NULL U / V or U == V. */
+stmg_status stmg_wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V);
+
 /* ---- learned preconditioning stage (not part of the paper's method) ----------------
  * Network C(r) on a finest-level residual r ([n_t][N_x], FP64, 3D only):
  *   s = sqrt(mean(r^2)); h_0 = r / s (one channel per temporal DoF);

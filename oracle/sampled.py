@@ -1,0 +1,180 @@
+"""Single entries of the slab operator and of one additive Schwarz step, for problems whose
+assembled space-time matrices do not fit in host memory (test infrastructure, like the
+rest of this package).
+
+Each entry is computed from its definition by cell-local assembly.
+
+Operator (eq. lin-sys, S = M_T (x) A_h + N_T (x) M_h with Dirichlet rows kept as identity):
+  (S x)[i, g] = sum over cells K that contain node g, sum over j of
+                (M_T)_ij (A_K x_K^j)_g + (N_T)_ij (M_K x_K^j)_g        (g interior)
+  (S x)[i, g] = x[i, g]                                                (g on the boundary)
+where x_K^j is temporal plane j of x on the nodes of K with Dirichlet values read as zero.
+
+One additive Schwarz step from u = 0 (eqs. vanka0, vanka):
+  u[i, g] = omega * sum over cells K that contain g of (B_K^{-1} R_{K,m} r)[i - m n_c, g]
+with m the time cell of temporal DoF i, n_c temporal DoFs per time cell, and
+B_K = M_tau (x) (A_h)_KK + Ntilde (x) (M_h)_KK, the principal submatrix of the assembled
+operator on the interior nodes of K times one time cell; (A_h)_KK and (M_h)_KK are summed
+from the cell matrices of K and of every cell that shares nodes with K.  A Dirichlet DoF is
+its own 1x1 identity block: u = omega r there.
+"""
+from __future__ import annotations
+
+from typing import Dict, Iterable, List, Tuple
+
+import numpy as np
+
+from . import spacetime, spatial, temporal
+
+
+class Sampler:
+    """Cell matrices on demand for one configuration (finest level)."""
+
+    def __init__(self, cfg, verts, coef):
+        self.cfg = cfg
+        self.space = spacetime.fine_space(cfg, verts, coef)
+        self.slab = temporal.slab(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau, cfg.t0)
+        self.bmask = self.space.boundary_mask()
+        self.dofs = self.space.cell_dofs()
+        self._cache: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
+
+    # lattice helpers -----------------------------------------------------------------------
+    def node_coords(self, g: int) -> List[int]:
+        out = []
+        for m in self.space.nodes:
+            out.append(g % m)
+            g //= m
+        return out
+
+    def cell_index(self, cc) -> int:
+        idx, stride = 0, 1
+        for d, c in enumerate(cc):
+            idx += c * stride
+            stride *= self.space.cells[d]
+        return idx
+
+    def cells_of_node(self, g: int) -> List[int]:
+        p = self.space.p
+        per_dim = []
+        for d, x in enumerate(self.node_coords(g)):
+            cand = [x // p - 1, x // p] if x % p == 0 else [x // p]
+            per_dim.append([c for c in cand if 0 <= c < self.space.cells[d]])
+        out = [[]]
+        for opts in per_dim:
+            out = [o + [c] for o in out for c in opts]
+        return [self.cell_index(cc) for cc in out]
+
+    def neighbours(self, K: int) -> List[int]:
+        cc = []
+        k = K
+        for m in self.space.cells:
+            cc.append(k % m)
+            k //= m
+        out = [[]]
+        for d, c in enumerate(cc):
+            out = [o + [c + e] for o in out for e in (-1, 0, 1) if 0 <= c + e < self.space.cells[d]]
+        return [self.cell_index(v) for v in out]
+
+    def matrices(self, cells: Iterable[int]):
+        need = sorted(set(int(c) for c in cells) - set(self._cache))
+        if need:
+            M, A = spatial.cell_matrices(self.space, np.array(need, dtype=np.int64))
+            for c, m, a in zip(need, M, A):
+                self._cache[c] = (m, a)
+        return [self._cache[int(c)] for c in cells]
+
+    # sampled operator rows -------------------------------------------------------------------
+    def operator_entries(self, x: np.ndarray, samples) -> np.ndarray:
+        """(S x)[i, g] for each (i, g) in samples; x of shape (n_t, N_x)."""
+        x = x.reshape(self.slab.n_t, self.space.n_x)
+        out = np.zeros(len(samples))
+        for s, (i, g) in enumerate(samples):
+            if self.bmask[g]:
+                out[s] = x[i, g]
+                continue
+            val = 0.0
+            cells = self.cells_of_node(g)
+            for K, (Mk, Ak) in zip(cells, self.matrices(cells)):
+                d = self.dofs[K]
+                a = int(np.nonzero(d == g)[0][0])
+                xK = x[:, d] * (~self.bmask[d])[None, :]           # (n_t, n_s)
+                Ax = xK @ Ak[a]                                     # (A_K x^j)_g for every j
+                Mx = xK @ Mk[a]
+                val += self.slab.M_T[i] @ Ax + self.slab.N_T[i] @ Mx
+            out[s] = val
+        return out
+
+    # sampled additive Schwarz step -----------------------------------------------------------
+    def local_blocks(self, K: int):
+        """Interior node list of K and (A_h)_KK, (M_h)_KK on it (principal submatrices)."""
+        dK = self.dofs[K]
+        inner = dK[~self.bmask[dK]]
+        pos = {int(g): t for t, g in enumerate(inner)}
+        n = len(inner)
+        A = np.zeros((n, n))
+        M = np.zeros((n, n))
+        nb = self.neighbours(K)
+        for K2, (Mk, Ak) in zip(nb, self.matrices(nb)):
+            d2 = self.dofs[K2]
+            loc = np.array([pos.get(int(g), -1) for g in d2])
+            sel = np.nonzero(loc >= 0)[0]
+            if len(sel) == 0:
+                continue
+            ix = np.ix_(loc[sel], loc[sel])
+            A[ix] += Ak[np.ix_(sel, sel)]
+            M[ix] += Mk[np.ix_(sel, sel)]
+        return inner, A, M
+
+    def asm_entries(self, r: np.ndarray, omega: float, samples) -> np.ndarray:
+        """u[i, g] after one additive Schwarz step u = omega * ASM(r) from u = 0."""
+        r = r.reshape(self.slab.n_t, self.space.n_x)
+        nc = self.slab.nt_cell
+        out = np.zeros(len(samples))
+        for s, (i, g) in enumerate(samples):
+            if self.bmask[g]:
+                out[s] = omega * r[i, g]
+                continue
+            m, il = divmod(i, nc)
+            val = 0.0
+            for K in self.cells_of_node(g):
+                inner, A, M = self.local_blocks(K)
+                B = np.kron(self.slab.M_tau, A) + np.kron(self.slab.N_tilde, M)
+                rhs = r[m * nc:(m + 1) * nc][:, inner].ravel()          # [temporal][node]
+                sol = np.linalg.solve(B, rhs).reshape(nc, len(inner))
+                val += sol[il, int(np.nonzero(inner == g)[0][0])]
+            out[s] = omega * val
+        return out
+
+
+def sample_points(cfg, n_inner: int, n_boundary: int, seed: int):
+    """(temporal DoF, node) pairs: interior nodes of every kind (cell corners, edges, faces,
+    cell interiors) and a few Dirichlet nodes, drawn from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    nodes = [p * c + 1 for p, c in zip([cfg.p] * cfg.dim, cfg.n_cells[: cfg.dim])]
+    n_t = cfg.n_t
+    out = []
+    for t in range(n_inner):
+        kind = t % 4          # number of coordinates that sit on a cell boundary (0..3, capped at dim)
+        coords = []
+        for d in range(cfg.dim):
+            on = d < min(kind, cfg.dim)
+            while True:
+                x = int(rng.integers(1, nodes[d] - 1))
+                if (x % cfg.p == 0) == on or cfg.p == 1:
+                    break
+            coords.append(x)
+        g, stride = 0, 1
+        for d in range(cfg.dim):
+            g += coords[d] * stride
+            stride *= nodes[d]
+        out.append((int(rng.integers(0, n_t)), g))
+    for _ in range(n_boundary):
+        coords = [int(rng.integers(0, m)) for m in nodes]
+        d = int(rng.integers(0, cfg.dim))
+        coords[d] = 0 if rng.random() < 0.5 else nodes[d] - 1
+        g, stride = 0, 1
+        for dd in range(cfg.dim):
+            g += coords[dd] * stride
+            stride *= nodes[dd]
+        out.append((int(rng.integers(0, n_t)), g))
+    return out

@@ -97,10 +97,13 @@ class Space:
         idx = tuple(vc[:, :, d] for d in reversed(range(self.dim)))
         return self.verts[idx]
 
-    def coef_at(self, xi: np.ndarray) -> np.ndarray:
-        """Coefficient at reference points xi (n_q, dim) of every cell: (n_cells, n_q)."""
+    def coef_at(self, xi: np.ndarray, cells: Optional[np.ndarray] = None) -> np.ndarray:
+        """Coefficient at reference points xi (n_q, dim) of every cell (or of the listed
+        cells): (n_cells, n_q)."""
         r = self.ratio
         cc = self.cell_coords()
+        if cells is not None:
+            cc = cc[cells]
         sub = np.minimum(np.floor(xi * r).astype(np.int64), r - 1)      # (n_q, dim)
         fc = cc[:, None, :] * r + sub[None, :, :]
         idx = np.zeros(fc.shape[:2], dtype=np.int64)
@@ -133,9 +136,12 @@ def reference_tables(p: int, dim: int, nq: Optional[int] = None):
     return xi, W, Phi, G
 
 
-def jacobians(space: Space, xi: np.ndarray) -> np.ndarray:
-    """J[c, q] = d x / d xi (dim x dim) of the multilinear cell map at reference points xi."""
+def jacobians(space: Space, xi: np.ndarray, cells: Optional[np.ndarray] = None) -> np.ndarray:
+    """J[c, q] = d x / d xi (dim x dim) of the multilinear cell map at reference points xi
+    (every cell, or the listed cells)."""
     X = space.cell_vertices()                     # (nc, 2^d, d)
+    if cells is not None:
+        X = X[cells]
     d = space.dim
     nv = 2 ** d
     dN = np.zeros((xi.shape[0], nv, d))
@@ -152,16 +158,17 @@ def jacobians(space: Space, xi: np.ndarray) -> np.ndarray:
     return np.einsum("cvi,qvj->cqij", X, dN)
 
 
-def cell_matrices(space: Space):
-    """Element mass and stiffness matrices, each (n_cells, n_s, n_s), by Gauss quadrature."""
+def cell_matrices(space: Space, cells: Optional[np.ndarray] = None):
+    """Element mass and stiffness matrices, each (n_cells, n_s, n_s), by Gauss quadrature
+    (every cell, or only the listed linear cell indices, in that order)."""
     xi, W, Phi, G = reference_tables(space.p, space.dim)
-    J = jacobians(space, xi)
+    J = jacobians(space, xi, cells)
     det = np.linalg.det(J)
     if np.any(det <= 0):
         raise ValueError("inverted cell")
     Jinv = np.linalg.inv(J)
     K = np.einsum("cqik,cqjk->cqij", Jinv, Jinv)       # J^{-1} J^{-T}
-    rho = space.coef_at(xi)
+    rho = space.coef_at(xi, cells)
     wdet = W[None, :] * det
     Mk = np.einsum("qa,cq,qb->cab", Phi, wdet, Phi)
     Ak = np.zeros_like(Mk)

@@ -99,6 +99,8 @@ _SIGS = {
     "stmg_cnn_set_params": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "stmg_cnn_get_params": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "stmg_cnn_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "stmg_wave_velocity": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
     "stmg_cnn_param_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
                             ctypes.c_int),
     "stmg_cnn_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -284,6 +286,19 @@ class Handle:
         th = np.empty(self.cnn_nparam, dtype=np.float32)
         _check(self.lib.stmg_cnn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p), th.size))
         return th
+
+    def wave_velocity(self, U, V, u0=None, v0=None):
+        """V = velocity of the wave slab from displacement U (u0, v0: initial data or None)."""
+        import torch
+        self._sz(U, 0); self._sz(V, 0)
+        nx = self.info["n_x"][0]
+        for t in (u0, v0):
+            if t is not None and (t.numel() != nx or t.dtype != torch.float64 or not t.is_contiguous()):
+                raise ValueError(f"initial data must be contiguous float64 with {nx} entries")
+        p0 = _ptr(u0, torch.float64) if u0 is not None else None
+        p1 = _ptr(v0, torch.float64) if v0 is not None else None
+        _check(self.lib.stmg_wave_velocity(self.h, _ptr(U, torch.float64), p0, p1, _ptr(V, torch.float64)))
+        return V
 
     def cnn_forward(self, r, z):
         import torch

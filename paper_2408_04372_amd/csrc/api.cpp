@@ -283,6 +283,16 @@ stmg_status stmg_cnn_get_params(stmg_handle* h, float* params, int64_t n) {
   });
 }
 
+stmg_status stmg_wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (h->cfg.problem != STMG_WAVE) stmg::fail(STMG_E_UNSUPPORTED, "velocity recovery needs the wave problem");
+    if (!U || !V || (const void*)U == (const void*)V) stmg::fail(STMG_E_ARG, "bad U / V");
+    stmg::wave_velocity(h, U, u0, v0, V);
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_cnn_forward(stmg_handle* h, const double* r, double* z) {
   return guarded([&]() -> stmg_status {
     level_of(h, 0);

@@ -101,6 +101,7 @@ struct stmg_handle {
   double setup_seconds = 0.0;
   int64_t bytes_at_create = 0;
   stmg::CnnState* cnn = nullptr;
+  stmg::DevBuf vel;            // wave velocity recovery: M_T^{-1} A_T and the u0 / v0 weights
   ~stmg_handle();
 };
 
@@ -114,6 +115,7 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
 template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* coarse);
 void estimate_omegas(stmg_handle* h);
 stmg_status fgmres(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
+void wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V);
 // learned stage (cnn.hip)
 void cnn_create(stmg_handle* h, int n_layers, const int* channels);
 long long cnn_param_count(stmg_handle* h);

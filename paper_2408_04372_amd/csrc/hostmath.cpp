@@ -178,6 +178,9 @@ Temporal temporal(int problem, int method, int k, int c, double tau) {
     sub_M = Mat(nc, nc);
     sub_A = Mat(nc, nc);
     for (int i = 0; i < nc; ++i) sub_A(i, nc - 1) = -V0(0, i);   // -alpha e_N^T
+    T.alpha.assign(nc, 0.0);
+    T.beta.assign(nc, 0.0);
+    for (int i = 0; i < nc; ++i) T.alpha[i] = V0(0, i);
   } else {  // cGP(k): trial at k+1 Gauss-Lobatto points, test at the last k of them
     if (k < 1) fail(STMG_E_ARG, "cGP needs k >= 1");
     Vec trial = gauss_lobatto(k + 1);
@@ -206,6 +209,9 @@ Temporal temporal(int problem, int method, int k, int c, double tau) {
       sub_M(i, nc - 1) = Mf(i, 0);   // beta e_N^T: previous cell's last DoF is this cell's first
       sub_A(i, nc - 1) = Af(i, 0);   // alpha e_N^T
     }
+    T.alpha.assign(nc, 0.0);
+    T.beta.assign(nc, 0.0);
+    for (int i = 0; i < nc; ++i) { T.alpha[i] = Af(i, 0); T.beta[i] = Mf(i, 0); }
   }
   int n = nc * c;
   T.n_t = n;

@@ -36,6 +36,7 @@ struct Temporal {
   int n_t = 0, nt_cell = 0, c = 0;
   Mat M_T, A_T, N_T;      // n_t x n_t
   Mat M_tau, N_tilde;     // diagonal blocks (ASM local temporal factors)
+  Vec alpha, beta;        // coupling of the first time cell to u0 (alpha) and, for cGP, v0 / F0 (beta)
 };
 // problem: 0 heat, 1 wave; method: 0 dG, 1 cGP.
 Temporal temporal(int problem, int method, int k, int c, double tau);

@@ -167,3 +167,33 @@ def test_solve_fp32_preconditioner(name):
     print(name, info, "oracle residual", res, "error", err)
     assert res <= 1e-8
     assert info["rel_residual"] <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["wave2d_q3_dg2", "wave3d_q3_cgp2", "wave3d_q2_cgp1_ragged"])
+def test_wave_velocity_matches_oracle(name):
+    from oracle import rhs
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    rng = np.random.default_rng(31)
+    U = rng.standard_normal((cfg.n_t, op.n_x))
+    u0 = rng.standard_normal(op.n_x)
+    v0 = rng.standard_normal(op.n_x)
+    ref = rhs.velocity(op, U, u0, v0)
+    ref0 = rhs.velocity(op, U)
+    with _handle(cfg, verts, coef) as h:
+        V = torch.empty(U.size, dtype=torch.float64, device=DEV)
+        h.wave_velocity(_t(U).view(-1), V, _t(u0), _t(v0))
+        got = _np(V).reshape(ref.shape)
+        h.wave_velocity(_t(U).view(-1), V)
+        got0 = _np(V).reshape(ref.shape)
+    assert rel_err(got, ref) < 1e-12
+    assert rel_err(got0, ref0) < 1e-12
+
+
+def test_wave_velocity_rejects_heat():
+    from paper_2408_04372_amd import StmgError
+    cfg, verts, coef = problem("heat2d_q2_dg1")
+    with _handle(cfg, verts, coef) as h:
+        U = torch.zeros(h.size(0), dtype=torch.float64, device=DEV)
+        with pytest.raises(StmgError):
+            h.wave_velocity(U, torch.empty_like(U))

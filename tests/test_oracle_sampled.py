@@ -1,0 +1,44 @@
+"""Pins of the oracle's single-entry evaluation (oracle.sampled) against the assembled oracle."""
+import numpy as np
+import pytest
+
+import stmg_inputs as si
+from oracle import mg, sampled, spacetime
+
+CFGS = [
+    si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=2, n_cells=(3, 4, 3), tau=0.05,
+              perturb=0.12, coef="lognormal", coef_sigma=1.0, seed=41),
+    si.Config(dim=3, problem=1, time_method=1, p=3, k=2, n_time_cells=2, n_cells=(2, 3, 2), tau=0.04,
+              coef="lognormal_checker", coef_sigma=0.5, seed=42),
+    si.Config(dim=2, problem=1, time_method=0, p=4, k=2, n_time_cells=2, n_cells=(3, 3, 1), tau=0.05,
+              perturb=0.1, coef="lognormal", coef_sigma=0.8, seed=43),
+]
+
+
+@pytest.mark.parametrize("cfg", CFGS, ids=["heat3d_q2_dg1", "wave3d_q3_cgp2", "wave2d_q4_dg2"])
+def test_sampled_operator_and_asm_match_assembled(cfg):
+    verts, coef = si.draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    S = op.matrix()
+    smp = sampled.Sampler(cfg, verts, coef)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((cfg.n_t, op.n_x))
+    pts = sampled.sample_points(cfg, 24, 6, seed=7)
+    y = op.apply(x)
+    ys = smp.operator_entries(x, pts)
+    ref = np.array([y[i, g] for i, g in pts])
+    assert np.allclose(ys, ref, rtol=1e-12, atol=1e-12 * np.abs(y).max())
+    lev = mg.Level(op=op, S=S, blocks=mg.asm_blocks(op, S))
+    u = 0.37 * mg.asm_apply(lev, x.ravel()).reshape(cfg.n_t, op.n_x)
+    us = smp.asm_entries(x, 0.37, pts)
+    ref = np.array([u[i, g] for i, g in pts])
+    assert np.allclose(us, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max())
+
+
+def test_sample_points_cover_node_kinds():
+    cfg = CFGS[0]
+    pts = sampled.sample_points(cfg, 40, 8, seed=1)
+    smp = sampled.Sampler(cfg, *si.draw_problem(cfg))
+    counts = sorted({len(smp.cells_of_node(g)) for _, g in pts if not smp.bmask[g]})
+    assert counts == [1, 2, 4, 8]
+    assert sum(smp.bmask[g] for _, g in pts) == 8
