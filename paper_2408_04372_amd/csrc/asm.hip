@@ -269,130 +269,167 @@ constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
 // Same map as k_asm_apply, with both products on the matrix cores.  LDS holds one
 // [NSP][NTP + 1] panel: R^T (B operand of W = Q^T R^T), then W (B operand of Z = Q W),
 // then Z for the write-back.  Wave w owns the M tiles w, w + 4 and every N tile, and
-// loads its whole A strip (all K steps) before issuing the products.  Global traffic
-// walks the lattice with the node index fastest.
-template <class T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_asm_mfma(GeomDesc g, ColourSet cs, int n_t, int nt_cell, int NSP,
-                                                  int NTP, const T* __restrict__ Q,
-                                                  const T* __restrict__ Tinv, const T* __restrict__ r,
-                                                  T* __restrict__ u, T omega, int nblocks) {
+// loads its whole A strip (all K steps) before issuing the products.  The cell size
+// (DIM, N) and the padded temporal width NTP are compile-time, so every index split is a
+// multiply-shift; each thread keeps one local node and walks the temporal planes, so the
+// node offset and its Dirichlet flag are computed once.
+template <class T, int DIM, int N, int NTP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_asm_mfma(
+    GeomDesc g, ColourSet cs, int n_t, int nt_cell, const T* __restrict__ Q, const T* __restrict__ Tinv,
+    const T* __restrict__ r, T* __restrict__ u, T omega, int nblocks) {
   typedef typename Mma<T>::v4 v4;
+  constexpr int NS = DIM == 3 ? N * N * N : N * N;
+  constexpr int NSP = (NS + 15) / 16 * 16;
+  constexpr int LD = NTP + 1;
+  constexpr int MT = NSP / 16, NTt = NTP / 16, KS = NSP / 4;
+  constexpr int JSTEP = 256 / NSP;
+  static_assert(MT <= 4 * MAXM && NTt <= MAXNT && KS <= MAXK && 256 % NSP == 0, "cell too large");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = reinterpret_cast<T*>(smem_raw);    // [NSP][LD]
-  const int LD = NTP + 1;
-  const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
   const long long li = xcd_swizzle(blockIdx.x, nblocks);
   if (li >= cs.count) return;
   int cx, cy, cz;
   const long long cell = colour_cell(cs, g, li, cx, cy, cz);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // P = R^T (zero padded; Dirichlet nodes read as zero), node index fastest
-  for (int idx = tid; idx < NTP * NSP; idx += 256) {
-    int j = idx / NSP, a = idx - j * NSP;
+  // this thread's local node a and temporal start j0
+  const int a = tid % NSP, j0 = tid / NSP;
+  bool in = false;
+  long long node = 0;
+  if (a < NS) {
+    constexpr int p = N - 1;
+    const int lx = a % N, ly = (a / N) % N, lz = DIM == 3 ? a / (N * N) : 0;
+    const int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+    in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 &&
+         (DIM == 2 || (gz != 0 && gz != g.nn[2] - 1));
+    node = ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
+  }
+  // P = R^T (zero padded; Dirichlet nodes read as zero)
+#pragma unroll 4
+  for (int j = j0; j < NTP; j += JSTEP) {
     T v = 0;
-    if (a < ns && j < n_t) {
-      bool in;
-      long long node = node_of(g, cx, cy, cz, a, in);
-      if (in) v = r[(long long)j * g.nx + node];
-    }
+    if (in && j < n_t) v = r[(long long)j * g.nx + node];
     P[a * LD + j] = v;
   }
   __syncthreads();
-  const T* Qc = Q + (size_t)cell * ns * ns;    // column-major: Q(a, s) = Qc[s * ns + a]
-  const int MT = NSP / 16, NTt = NTP / 16, KS = NSP / 4;
+  const T* Qc = Q + (size_t)cell * NS * NS;    // column-major: Q(a, s) = Qc[s * NS + a]
   const int li16 = lane & 15, lk = lane >> 4;
   v4 acc[MAXM][MAXNT];
   // W[s][j] = sum_a Q(a, s) R^T[a][j]
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) {
-    int mt = wave + 4 * q;
+    const int mt = wave + 4 * q;
 #pragma unroll
-    for (int nt = 0; nt < MAXNT; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
+    for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
     if (mt >= MT) continue;
-    int s_idx = mt * 16 + li16;
-    T av[MAXK];
-    const T* qcol = Qc + (size_t)(s_idx < ns ? s_idx : 0) * ns;
+    const int s_idx = mt * 16 + li16;
+    T av[KS];
+    const T* qcol = Qc + (size_t)(s_idx < NS ? s_idx : 0) * NS;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      int a_idx = 4 * k + lk;
-      av[k] = (k < KS && s_idx < ns && a_idx < ns) ? qcol[a_idx] : (T)0;
+    for (int k = 0; k < KS; ++k) {
+      const int a_idx = 4 * k + lk;
+      av[k] = (s_idx < NS && a_idx < NS) ? qcol[a_idx] : (T)0;
     }
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      if (k < KS) {
-        const T* prow = P + (4 * k + lk) * LD + li16;
+    for (int k = 0; k < KS; ++k) {
+      const T* prow = P + (4 * k + lk) * LD + li16;
 #pragma unroll
-        for (int nt = 0; nt < MAXNT; ++nt)
-          if (nt < NTt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
-      }
+      for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) {
-    int mt = wave + 4 * q;
+    const int mt = wave + 4 * q;
     if (mt >= MT) continue;
 #pragma unroll
-    for (int nt = 0; nt < MAXNT; ++nt) {
-      if (nt >= NTt) continue;
+    for (int nt = 0; nt < NTt; ++nt)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
-    }
   }
   __syncthreads();
   // per mode s and time cell m: W[s, m, :] <- (lambda_s M_tau + N~)^{-1} W[s, m, :]
   switch (nt_cell) {
-    case 1: temporal_modes<T, 1>(P, LD, Tinv, cell, ns, n_t, tid); break;
-    case 2: temporal_modes<T, 2>(P, LD, Tinv, cell, ns, n_t, tid); break;
-    case 3: temporal_modes<T, 3>(P, LD, Tinv, cell, ns, n_t, tid); break;
-    case 4: temporal_modes<T, 4>(P, LD, Tinv, cell, ns, n_t, tid); break;
-    case 5: temporal_modes<T, 5>(P, LD, Tinv, cell, ns, n_t, tid); break;
-    default: temporal_modes<T, 6>(P, LD, Tinv, cell, ns, n_t, tid); break;
+    case 1: temporal_modes<T, 1>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    case 2: temporal_modes<T, 2>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    case 3: temporal_modes<T, 3>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    case 4: temporal_modes<T, 4>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    case 5: temporal_modes<T, 5>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    default: temporal_modes<T, 6>(P, LD, Tinv, cell, NS, n_t, tid); break;
   }
   __syncthreads();
   // Z[a][j] = sum_s Q(a, s) W[s][j]
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) {
-    int mt = wave + 4 * q;
+    const int mt = wave + 4 * q;
 #pragma unroll
-    for (int nt = 0; nt < MAXNT; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
+    for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
     if (mt >= MT) continue;
-    int a_idx = mt * 16 + li16;
-    T av[MAXK];
+    const int a_idx = mt * 16 + li16;
+    T av[KS];
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      int s_idx = 4 * k + lk;
-      av[k] = (k < KS && a_idx < ns && s_idx < ns) ? Qc[(size_t)s_idx * ns + a_idx] : (T)0;
+    for (int k = 0; k < KS; ++k) {
+      const int s_idx = 4 * k + lk;
+      av[k] = (a_idx < NS && s_idx < NS) ? Qc[(size_t)s_idx * NS + a_idx] : (T)0;
     }
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-      if (k < KS) {
-        const T* prow = P + (4 * k + lk) * LD + li16;
+    for (int k = 0; k < KS; ++k) {
+      const T* prow = P + (4 * k + lk) * LD + li16;
 #pragma unroll
-        for (int nt = 0; nt < MAXNT; ++nt)
-          if (nt < NTt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
-      }
+      for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
     }
   }
   __syncthreads();
-  // Z into LDS, then added to the interior nodes with the node index fastest
+  // Z into LDS, then added to the interior nodes
 #pragma unroll
   for (int q = 0; q < MAXM; ++q) {
-    int mt = wave + 4 * q;
+    const int mt = wave + 4 * q;
     if (mt >= MT) continue;
 #pragma unroll
-    for (int nt = 0; nt < MAXNT; ++nt) {
-      if (nt >= NTt) continue;
+    for (int nt = 0; nt < NTt; ++nt)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
-    }
   }
   __syncthreads();
-  for (int idx = tid; idx < n_t * ns; idx += 256) {
-    int j = idx / ns, a = idx - j * ns;
-    bool in;
-    long long node = node_of(g, cx, cy, cz, a, in);
-    if (in) u[(long long)j * g.nx + node] += omega * P[a * LD + j];
+  if (in) {
+#pragma unroll 4
+    for (int j = j0; j < n_t; j += JSTEP) u[(long long)j * g.nx + node] += omega * P[a * LD + j];
+  }
+}
+
+template <class T, int DIM, int N, int NTP>
+void launch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
+                     const T* r, T* u, T omega, hipStream_t s) {
+  constexpr int NS = DIM == 3 ? N * N * N : N * N;
+  constexpr int NSP = (NS + 15) / 16 * 16;
+  int nb = (int)cs.count;
+  hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(256), sizeof(T) * (size_t)NSP * (NTP + 1), s,
+                     g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, nb);
+}
+
+template <class T, int DIM, int N>
+void launch_asm_mfma_nt(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
+                        const T* r, T* u, T omega, hipStream_t s) {
+  if (n_t <= 16) launch_asm_mfma<T, DIM, N, 16>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
+  else launch_asm_mfma<T, DIM, N, 32>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
+}
+
+template <class T>
+void dispatch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
+                       const T* r, T* u, T omega, hipStream_t s) {
+  if (g.dim == 3) {
+    switch (g.n) {
+      case 2: launch_asm_mfma_nt<T, 3, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 3: launch_asm_mfma_nt<T, 3, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 4: launch_asm_mfma_nt<T, 3, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      default: launch_asm_mfma_nt<T, 3, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+    }
+  } else {
+    switch (g.n) {
+      case 2: launch_asm_mfma_nt<T, 2, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 3: launch_asm_mfma_nt<T, 2, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 4: launch_asm_mfma_nt<T, 2, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      default: launch_asm_mfma_nt<T, 2, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+    }
   }
 }
 
@@ -448,8 +485,7 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
     if (cs.count == 0) continue;
     int nb = (int)cs.count;
     if (use_mfma)
-      hipLaunchKernelGGL(k_asm_mfma<T>, dim3(nb), dim3(256), sizeof(T) * (size_t)NSP * (NTP + 1), s, g, cs, n_t,
-                         nt_cell, NSP, NTP, Q, Tinv, r, u, omega, nb);
+      dispatch_asm_mfma<T>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
     else
       hipLaunchKernelGGL(k_asm_apply<T>, dim3(nb), dim3(ABS), lds, s, g, cs, n_t, nt_cell, Q, Tinv, r, u,
                          omega, nb);

@@ -3,6 +3,8 @@
 // products / updates for the Gram-Schmidt passes of FGMRES.  Reductions are two
 // stage (fixed grid of partial sums, then one block per result) so results do not
 // depend on atomics ordering.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace stmg {
@@ -62,27 +64,33 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // partial dots of up to JC vectors against w: part[block * JC + j]
-__global__ void k_dot_part(const double* __restrict__ V, long long ldv, int kc,
-                           const double* __restrict__ w, long long n, double* __restrict__ part, int self) {
+// The multi-vector kernels take the vector count as a template argument, so all loads of
+// one element index are issued back to back (no per-vector branches).
+template <int KC>
+__global__ void k_dot_part(const double* __restrict__ V, long long ldv, const double* __restrict__ w, long long n,
+                           double* __restrict__ part, int self) {
   __shared__ double sh[BS / 64];
-  double acc[JC];
+  double acc[KC];
   double ww = 0.0;
 #pragma unroll
-  for (int j = 0; j < JC; ++j) acc[j] = 0.0;
+  for (int j = 0; j < KC; ++j) acc[j] = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     double wi = w[i];
+    double v[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) v[j] = V[j * ldv + i];
     ww += wi * wi;
 #pragma unroll
-    for (int j = 0; j < JC; ++j)
-      if (j < kc) acc[j] += V[j * ldv + i] * wi;
+    for (int j = 0; j < KC; ++j) acc[j] += v[j] * wi;
   }
-  for (int j = 0; j < kc; ++j) {
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
     double s = block_sum(acc[j], sh);
     if (threadIdx.x == 0) part[blockIdx.x * PS + j] = s;
   }
   if (self) {
     double s = block_sum(ww, sh);
-    if (threadIdx.x == 0) part[blockIdx.x * PS + kc] = s;
+    if (threadIdx.x == 0) part[blockIdx.x * PS + KC] = s;
   }
 }
 
@@ -95,39 +103,54 @@ __global__ void k_dot_final(const double* __restrict__ part, int nblocks, int kc
   if (threadIdx.x == 0) out[j] = s;
 }
 
-__global__ void k_multi_axpy_neg(const double* __restrict__ V, long long ldv, int k,
-                                 const double* __restrict__ h, double* __restrict__ w, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double s = w[i];
-    for (int j = 0; j < k; ++j) s -= h[j] * V[j * ldv + i];
-    w[i] = s;
-  }
-}
-
-// the update above fused with the partial sums of the new ||w||^2 and a non-finite flag
-__global__ void k_multi_axpy_neg_norm(const double* __restrict__ V, long long ldv, int k,
-                                      const double* __restrict__ h, double* __restrict__ w, long long n,
-                                      double* __restrict__ part) {
+// w -= sum_j h[j] V_j; with NORM also the partial sums of the new ||w||^2 and a non-finite flag
+template <int KC, bool NORM>
+__global__ void k_multi_axpy_neg(const double* __restrict__ V, long long ldv, const double* __restrict__ h,
+                                 double* __restrict__ w, long long n, double* __restrict__ part) {
   __shared__ double sh[BS / 64];
+  double c[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) c[j] = h[j];
   double acc = 0.0, bad = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double v[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) v[j] = V[j * ldv + i];
     double s = w[i];
-    for (int j = 0; j < k; ++j) s -= h[j] * V[j * ldv + i];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) s -= c[j] * v[j];
     w[i] = s;
-    if (!isfinite(s)) bad = 1.0;
-    else acc += s * s;
+    if (NORM) {
+      if (!isfinite(s)) bad = 1.0;
+      else acc += s * s;
+    }
   }
-  double a = block_sum(acc, sh);
-  double b = block_sum(bad, sh);
-  if (threadIdx.x == 0) { part[blockIdx.x * PS] = a; part[blockIdx.x * PS + 1] = b; }
+  if (NORM) {
+    double a = block_sum(acc, sh);
+    double b = block_sum(bad, sh);
+    if (threadIdx.x == 0) { part[blockIdx.x * PS] = a; part[blockIdx.x * PS + 1] = b; }
+  }
 }
 
-template <class T>
-__global__ void k_multi_axpy_acc(const T* __restrict__ Z, long long ldz, int k,
-                                 const double* __restrict__ y, double* __restrict__ x, long long n) {
+// K from 1 to JC, chosen at run time
+template <int K, class F> void by_count(int k, F&& f) {
+  if (k == K) f(std::integral_constant<int, K>{});
+  else if constexpr (K > 1) by_count<K - 1>(k, f);
+}
+
+template <class T, int KC>
+__global__ void k_multi_axpy_acc(const T* __restrict__ Z, long long ldz, const double* __restrict__ y,
+                                 double* __restrict__ x, long long n) {
+  double c[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) c[j] = y[j];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double v[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) v[j] = (double)Z[j * ldz + i];
     double s = x[i];
-    for (int j = 0; j < k; ++j) s += y[j] * (double)Z[j * ldz + i];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) s += c[j] * v[j];
     x[i] = s;
   }
 }
@@ -198,7 +221,9 @@ void multi_dot(const double* V, long long ldv, int k, const double* w, long long
   for (int j0 = 0; j0 < k; j0 += JC) {
     int kc = k - j0 < JC ? k - j0 : JC;
     int sf = (self && j0 + kc == k) ? 1 : 0;     // w . w with the last group, into out[k]
-    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(BS), 0, s, V + j0 * ldv, ldv, kc, w, n, part, sf);
+    by_count<JC>(kc, [&](auto K) {
+      hipLaunchKernelGGL((k_dot_part<decltype(K)::value>), dim3(nb), dim3(BS), 0, s, V + j0 * ldv, ldv, w, n, part, sf);
+    });
     STMG_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_dot_final, dim3(kc + sf), dim3(BS), 0, s, part, (int)nb, kc + sf, out + j0);
     STMG_CHECK_LAUNCH();
@@ -208,16 +233,33 @@ void multi_dot(const double* V, long long ldv, int k, const double* w, long long
 void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, double* w, long long n,
                     hipStream_t s) {
   if (n <= 0 || k <= 0) return;
-  hipLaunchKernelGGL(k_multi_axpy_neg, dim3(grid_for(n)), dim3(BS), 0, s, V, ldv, k, h, w, n);
-  STMG_CHECK_LAUNCH();
+  for (int j0 = 0; j0 < k; j0 += JC) {
+    int kc = k - j0 < JC ? k - j0 : JC;
+    by_count<JC>(kc, [&](auto K) {
+      hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, false>), dim3(grid_for(n)), dim3(BS), 0, s,
+                         V + j0 * ldv, ldv, h + j0, w, n, (double*)nullptr);
+    });
+    STMG_CHECK_LAUNCH();
+  }
 }
 
 void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h, double* w, long long n,
                          double* out, double* part, hipStream_t s) {
   unsigned nb = grid_for(n);
   if (nb > RED_BLOCKS) nb = RED_BLOCKS;
-  hipLaunchKernelGGL(k_multi_axpy_neg_norm, dim3(nb), dim3(BS), 0, s, V, ldv, k, h, w, n, part);
-  STMG_CHECK_LAUNCH();
+  for (int j0 = 0; j0 < k; j0 += JC) {
+    int kc = k - j0 < JC ? k - j0 : JC;
+    const bool last = j0 + kc == k;
+    by_count<JC>(kc, [&](auto K) {
+      if (last)
+        hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, true>), dim3(nb), dim3(BS), 0, s,
+                           V + j0 * ldv, ldv, h + j0, w, n, part);
+      else
+        hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, false>), dim3(grid_for(n)), dim3(BS), 0, s,
+                           V + j0 * ldv, ldv, h + j0, w, n, (double*)nullptr);
+    });
+    STMG_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(k_dot_final, dim3(2), dim3(BS), 0, s, part, (int)nb, 2, out);
   STMG_CHECK_LAUNCH();
 }
@@ -226,8 +268,14 @@ template <class T>
 void multi_axpy_acc(const T* Z, long long ldz, int k, const double* y, double* x, long long n,
                     hipStream_t s) {
   if (n <= 0 || k <= 0) return;
-  hipLaunchKernelGGL(k_multi_axpy_acc<T>, dim3(grid_for(n)), dim3(BS), 0, s, Z, ldz, k, y, x, n);
-  STMG_CHECK_LAUNCH();
+  for (int j0 = 0; j0 < k; j0 += JC) {
+    int kc = k - j0 < JC ? k - j0 : JC;
+    by_count<JC>(kc, [&](auto K) {
+      hipLaunchKernelGGL((k_multi_axpy_acc<T, decltype(K)::value>), dim3(grid_for(n)), dim3(BS), 0, s,
+                         Z + j0 * ldz, ldz, y + j0, x, n);
+    });
+    STMG_CHECK_LAUNCH();
+  }
 }
 
 template <class T> void norm2_check(const T* x, long long n, double* out, double* part, hipStream_t s) {
