@@ -138,7 +138,7 @@ template <class T>
 __global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, ColourSet cs, int n_t, int nt_cell,
                                                    const T* __restrict__ Q, const T* __restrict__ Tinv,
                                                    const T* __restrict__ r, T* __restrict__ u, T omega,
-                                                   int nblocks) {
+                                                   int nblocks, T* __restrict__ cellbuf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
   T* R = reinterpret_cast<T*>(smem_raw);     // [n_t][ns]
@@ -210,7 +210,13 @@ __global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, ColourSet cs, int
     }
     bool in;
     long long node = node_of(g, cx, cy, cz, o, in);
-    if (in) {
+    if (cellbuf) {
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        int j = jg + jj * JG;
+        if (j < n_t) cellbuf[(cell * n_t + j) * ns + o] = omega * acc[jj];
+      }
+    } else if (in) {
 #pragma unroll
       for (int jj = 0; jj < JMAX; ++jj) {
         int j = jg + jj * JG;
@@ -276,7 +282,7 @@ constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
 template <class T, int DIM, int N, int NTP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_asm_mfma(
     GeomDesc g, ColourSet cs, int n_t, int nt_cell, const T* __restrict__ Q, const T* __restrict__ Tinv,
-    const T* __restrict__ r, T* __restrict__ u, T omega, int nblocks) {
+    const T* __restrict__ r, T* __restrict__ u, T omega, int nblocks, T* __restrict__ cellbuf) {
   typedef typename Mma<T>::v4 v4;
   constexpr int NS = DIM == 3 ? N * N * N : N * N;
   constexpr int NSP = (NS + 15) / 16 * 16;
@@ -390,7 +396,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
       for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
   }
   __syncthreads();
-  if (in) {
+  if (cellbuf) {
+    if (a < NS) {
+#pragma unroll 4
+      for (int j = j0; j < n_t; j += JSTEP) cellbuf[(cell * n_t + j) * NS + a] = omega * P[a * LD + j];
+    }
+  } else if (in) {
 #pragma unroll 4
     for (int j = j0; j < n_t; j += JSTEP) u[(long long)j * g.nx + node] += omega * P[a * LD + j];
   }
@@ -398,37 +409,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 
 template <class T, int DIM, int N, int NTP>
 void launch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
-                     const T* r, T* u, T omega, hipStream_t s) {
+                     const T* r, T* u, T omega, hipStream_t s, T* cb) {
   constexpr int NS = DIM == 3 ? N * N * N : N * N;
   constexpr int NSP = (NS + 15) / 16 * 16;
   int nb = (int)cs.count;
   hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(256), sizeof(T) * (size_t)NSP * (NTP + 1), s,
-                     g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, nb);
+                     g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, nb, cb);
 }
 
 template <class T, int DIM, int N>
 void launch_asm_mfma_nt(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
-                        const T* r, T* u, T omega, hipStream_t s) {
-  if (n_t <= 16) launch_asm_mfma<T, DIM, N, 16>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
-  else launch_asm_mfma<T, DIM, N, 32>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
+                        const T* r, T* u, T omega, hipStream_t s, T* cb) {
+  if (n_t <= 16) launch_asm_mfma<T, DIM, N, 16>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb);
+  else launch_asm_mfma<T, DIM, N, 32>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb);
 }
 
 template <class T>
 void dispatch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cell, const T* Q, const T* Tinv,
-                       const T* r, T* u, T omega, hipStream_t s) {
+                       const T* r, T* u, T omega, hipStream_t s, T* cb) {
   if (g.dim == 3) {
     switch (g.n) {
-      case 2: launch_asm_mfma_nt<T, 3, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      case 3: launch_asm_mfma_nt<T, 3, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      case 4: launch_asm_mfma_nt<T, 3, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      default: launch_asm_mfma_nt<T, 3, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 2: launch_asm_mfma_nt<T, 3, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      case 3: launch_asm_mfma_nt<T, 3, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      case 4: launch_asm_mfma_nt<T, 3, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      default: launch_asm_mfma_nt<T, 3, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
     }
   } else {
     switch (g.n) {
-      case 2: launch_asm_mfma_nt<T, 2, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      case 3: launch_asm_mfma_nt<T, 2, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      case 4: launch_asm_mfma_nt<T, 2, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
-      default: launch_asm_mfma_nt<T, 2, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s); break;
+      case 2: launch_asm_mfma_nt<T, 2, 2>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      case 3: launch_asm_mfma_nt<T, 2, 3>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      case 4: launch_asm_mfma_nt<T, 2, 4>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
+      default: launch_asm_mfma_nt<T, 2, 5>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cb); break;
     }
   }
 }
@@ -470,7 +481,7 @@ void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s) {
 
 template <class T>
 void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
-               T omega, hipStream_t s) {
+               T omega, hipStream_t s, T* cellbuf) {
   int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
   int JG = ABS / ns > 0 ? ABS / ns : 1;
   if ((n_t + JG - 1) / JG > JMAX) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the smoother kernel");
@@ -480,17 +491,20 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
   const bool use_mfma = n_t >= 8 && NSP <= 16 * 4 * MAXM && NTP <= 16 * MAXNT && NSP <= 4 * MAXK &&
                         nt_cell <= 6;
   // colours of cells without shared nodes: block corrections are added without atomics
-  for (int colour = 0; colour < n_colours(g.dim); ++colour) {
-    ColourSet cs = colour_set(g, colour);
+  // (with a per-cell buffer: every cell in one launch, then a node gather)
+  const int nsets = cellbuf ? 1 : n_colours(g.dim);
+  for (int colour = 0; colour < nsets; ++colour) {
+    ColourSet cs = cellbuf ? all_cells(g) : colour_set(g, colour);
     if (cs.count == 0) continue;
     int nb = (int)cs.count;
     if (use_mfma)
-      dispatch_asm_mfma<T>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s);
+      dispatch_asm_mfma<T>(g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, s, cellbuf);
     else
       hipLaunchKernelGGL(k_asm_apply<T>, dim3(nb), dim3(ABS), lds, s, g, cs, n_t, nt_cell, Q, Tinv, r, u,
-                         omega, nb);
+                         omega, nb, cellbuf);
     STMG_CHECK_LAUNCH();
   }
+  if (cellbuf) cell_gather<T>(g, n_t, cellbuf, u, s);
 }
 
 template void asm_tinv<double>(long long, int, int, const double*, const double*, const double*, double*, int*, hipStream_t);
@@ -498,8 +512,8 @@ template void asm_tinv<float>(long long, int, int, const double*, const double*,
 template void convert_from_double<float>(const double*, float*, long long, hipStream_t);
 template void convert_from_double<double>(const double*, double*, long long, hipStream_t);
 template void asm_apply<double>(const GeomDesc&, int, int, const double*, const double*, const double*,
-                                double*, double, hipStream_t);
+                                double*, double, hipStream_t, double*);
 template void asm_apply<float>(const GeomDesc&, int, int, const float*, const float*, const float*, float*,
-                               float, hipStream_t);
+                               float, hipStream_t, float*);
 
 }  // namespace stmg

@@ -54,6 +54,7 @@ template <class T> __device__ inline void atomic_add(T* p, T v) { unsafeAtomicAd
 // share no lattice node, so a launch over one colour may update its nodes without atomics.
 struct ColourSet {
   int colour = 0;
+  int step = 2;           // 2: one colour (every other cell per direction); 1: every cell
   int m[3] = {1, 1, 1};   // cells of this parity per direction
   long long count = 0;
 };
@@ -68,15 +69,27 @@ inline ColourSet colour_set(const GeomDesc& g, int colour) {
   }
   return c;
 }
+// every cell in one set (used with per-cell output buffers, where no two cells write one node)
+inline ColourSet all_cells(const GeomDesc& g) {
+  ColourSet c;
+  c.step = 1;
+  c.count = 1;
+  for (int d = 0; d < 3; ++d) {
+    c.m[d] = (d < g.dim) ? g.nc[d] : 1;
+    c.count *= c.m[d];
+  }
+  return c;
+}
 __device__ inline long long colour_cell(const ColourSet& cs, const GeomDesc& g, long long li, int& cx,
                                         int& cy, int& cz) {
   int ix = (int)(li % cs.m[0]);
   long long r = li / cs.m[0];
   int iy = (int)(r % cs.m[1]);
   int iz = (int)(r / cs.m[1]);
-  cx = 2 * ix + (cs.colour & 1);
-  cy = 2 * iy + ((cs.colour >> 1) & 1);
-  cz = 2 * iz + ((cs.colour >> 2) & 1);
+  const int c = cs.step == 2 ? cs.colour : 0;
+  cx = cs.step * ix + (c & 1);
+  cy = cs.step * iy + ((c >> 1) & 1);
+  cz = cs.step * iz + ((c >> 2) & 1);
   return ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
 }
 inline int n_colours(int dim) { return dim == 3 ? 8 : 4; }

@@ -24,6 +24,7 @@ struct LevelData {            // precision-dependent data of one level
   DevBuf Q, Tinv;             // smoother factors (not on the coarsest level)
   DevBuf u, r, f, tmpA, tmpB; // V-cycle work vectors
   DevBuf Cinv;                // coarsest level only: dense inverse on interior DoFs
+  DevBuf cellbuf;             // per-cell contributions (levels with few cells, see st_apply)
 };
 
 struct Level {

@@ -309,6 +309,10 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
   d.u.alloc(n);
   d.r.alloc(n);
   d.f.alloc(n);
+  if (L.g.ncells <= TWO_PHASE_MAX_CELLS) {
+    const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
+    d.cellbuf.alloc(sizeof(T) * L.g.ncells * n_t * nq);
+  }
   if (!coarsest) {
     d.tmpA.alloc(n);
     d.tmpB.alloc(n);
@@ -458,7 +462,7 @@ template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
   long long n = L.nst(h->tm.n_t);
   fill<T>(y, (T)0, n, s);
   if (level == 0) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(h), x, y, (T)1, s);
+  st_apply<T>(L.g, L.lt, tdev<T>(h), x, y, (T)1, s, ldata<T>(L).cellbuf.template as<T>());
   if (level == 0) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)1, x, (T)0, y, s);
 }
@@ -470,7 +474,7 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
   copy<T>(f, r, n, s);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(h), u, r, (T)-1, s);
+  st_apply<T>(L.g, L.lt, tdev<T>(h), u, r, (T)-1, s, ldata<T>(L).cellbuf.template as<T>());
   if (fine) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)-1, u, (T)1, r, s);
 }
@@ -482,7 +486,7 @@ template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T*
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(1, h->stream);
   asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
-               (T)L.omega, h->stream);
+               (T)L.omega, h->stream, d.cellbuf.template as<T>());
   if (fine) h->ktimer.end(h->stream);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)L.omega, r, (T)1, u, h->stream);
   h->timer.mark(TB_GMG, h->stream);

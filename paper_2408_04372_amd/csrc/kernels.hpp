@@ -18,9 +18,17 @@ LevelTables make_level_tables(int p);
 
 // ---- operator (op_apply.hip) ----------------------------------------------------------
 // y += scale * S_interior x : interior rows only, Dirichlet columns ignored.
+// With cellbuf (ncells * n_t * (p+1)^d entries) every cell writes its contribution there in
+// one launch and a node gather adds them to y (coarse levels: two launches instead of one
+// per colour); without it the cells are processed colour by colour.
 template <class T>
 void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
-              T scale, hipStream_t s);
+              T scale, hipStream_t s, T* cellbuf = nullptr);
+// Levels with at most this many cells use the per-cell buffer path.
+constexpr long long TWO_PHASE_MAX_CELLS = 4096;
+// y[j][g] += sum over the cells K containing interior node g of cb[K][j][local index of g]
+// (fixed cell order); Dirichlet nodes untouched.
+template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s);
 
 // ---- vector kernels (blas.hip) --------------------------------------------------------------
 template <class T> void fill(T* y, T v, long long n, hipStream_t s);
@@ -79,9 +87,10 @@ void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double*
               T* Tinv, int* bad, hipStream_t s);
 template <class Tout> void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s);
 // u += omega * sum_K R_K^T (I (x) Q_K) Tinv_K (I (x) Q_K^T) R_K r on interior rows.
+// cellbuf: as for st_apply (per-cell corrections, then a node gather).
 template <class T>
 void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
-               T omega, hipStream_t s);
+               T omega, hipStream_t s, T* cellbuf = nullptr);
 
 // ---- coarse solve (coarse.hip) ---------------------------------------------------------------------
 // z[idx[i]] = sum_j Cinv[i][j] f[idx[j]] for the m interior DoFs of the coarsest level.

@@ -32,6 +32,7 @@ struct OpArgs {
   TemporalDev<T> tp;
   const T* x;
   T* y;
+  T* cellbuf;     // non-null: write each cell's contribution to cellbuf[cell][n_t][NQ]
   T scale;
   int cpw;        // cells per workgroup
   int nblocks;
@@ -359,6 +360,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
       for (int x = 0; x < N; ++x) scr[(t * N + y) * N + x] = t2[y][x];
   }
   __syncthreads();
+  if (A.cellbuf) {
+    for (int lc2 = 0; lc2 < ncell; ++lc2) {
+      int cx, cy, cz;
+      const long long cell = colour_cell(cs, g, li0 + lc2, cx, cy, cz);
+      const T* src = xs + (size_t)lc2 * n_t * NQ;
+      T* dst = A.cellbuf + cell * n_t * NQ;
+      for (int idx = tid; idx < n_t * NQ; idx += nthr) dst[idx] = A.scale * src[idx];
+    }
+    return;
+  }
   for (int lc2 = 0; lc2 < ncell; ++lc2) {
     int cx, cy, cz;
     colour_cell(cs, g, li0 + lc2, cx, cy, cz);
@@ -468,6 +479,15 @@ __global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A, ColourSet cs) {
       for (int qx = 0; qx < N; ++qx) bh[qy][qx] += t0[qy][qx] + ah[qy][qx];
     rows_t<T, N>(S, bh, t0);    // [y][qx]
     cols_t<T, N>(S, t0, ah);    // [y][x]
+    if (A.cellbuf) {
+      const long long cell = (long long)cy * g.nc[0] + cx;
+      T* cb = A.cellbuf + (cell * n_t + i) * NQ;
+#pragma unroll
+      for (int y = 0; y < N; ++y)
+#pragma unroll
+        for (int x = 0; x < N; ++x) cb[y * N + x] = A.scale * ah[y][x];
+      continue;
+    }
     T* yi = A.y + (long long)i * plane + base;
 #pragma unroll
     for (int y = 0; y < N; ++y)
@@ -507,13 +527,14 @@ int pick_cpw(int teams, int n_t) {
 
 template <class T, int N>
 void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp,
-                  const T* x, T* y, T scale, hipStream_t s) {
+                  const T* x, T* y, T scale, hipStream_t s, T* cellbuf) {
   OpArgs<T, N> A;
   A.tab = make_tables<T, N>(lt);
   A.g = g;
   A.tp = tp;
   A.x = x;
   A.y = y;
+  A.cellbuf = cellbuf;
   A.scale = scale;
   size_t lds;
   int threads = 64;
@@ -540,34 +561,36 @@ void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>
     A.cpw = pick_cpw(64, tp.n_t);
     lds = sizeof(T) * ((size_t)A.cpw * NQ * 4);
   }
-  for (int colour = 0; colour < n_colours(g.dim); ++colour) {
-    ColourSet cs = colour_set(g, colour);
+  const int nsets = cellbuf ? 1 : n_colours(g.dim);
+  for (int colour = 0; colour < nsets; ++colour) {
+    ColourSet cs = cellbuf ? all_cells(g) : colour_set(g, colour);
     if (cs.count == 0) continue;
     A.nblocks = ceil_div(cs.count, A.cpw);
     if (g.dim == 3) hipLaunchKernelGGL((st_apply3<T, N>), dim3(A.nblocks), dim3(threads), lds, s, A, cs);
     else hipLaunchKernelGGL((st_apply2<T, N>), dim3(A.nblocks), dim3(64), lds, s, A, cs);
     STMG_CHECK_LAUNCH();
   }
+  if (cellbuf) cell_gather<T>(g, tp.n_t, cellbuf, y, s);
 }
 
 }  // namespace
 
 template <class T>
 void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
-              T scale, hipStream_t s) {
+              T scale, hipStream_t s, T* cellbuf) {
   if (g.ncells == 0 || tp.n_t == 0) return;
   switch (g.n) {
-    case 2: launch_apply<T, 2>(g, lt, tp, x, y, scale, s); break;
-    case 3: launch_apply<T, 3>(g, lt, tp, x, y, scale, s); break;
-    case 4: launch_apply<T, 4>(g, lt, tp, x, y, scale, s); break;
-    case 5: launch_apply<T, 5>(g, lt, tp, x, y, scale, s); break;
+    case 2: launch_apply<T, 2>(g, lt, tp, x, y, scale, s, cellbuf); break;
+    case 3: launch_apply<T, 3>(g, lt, tp, x, y, scale, s, cellbuf); break;
+    case 4: launch_apply<T, 4>(g, lt, tp, x, y, scale, s, cellbuf); break;
+    case 5: launch_apply<T, 5>(g, lt, tp, x, y, scale, s, cellbuf); break;
     default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
   }
 }
 
 template void st_apply<double>(const GeomDesc&, const LevelTables&, const TemporalDev<double>&,
-                               const double*, double*, double, hipStream_t);
+                               const double*, double*, double, hipStream_t, double*);
 template void st_apply<float>(const GeomDesc&, const LevelTables&, const TemporalDev<float>&,
-                              const float*, float*, float, hipStream_t);
+                              const float*, float*, float, hipStream_t, float*);
 
 }  // namespace stmg

@@ -10,36 +10,36 @@ namespace stmg {
 
 namespace {
 
+// grid: x = chunks of the (i0, i1) output plane, y = i2, z = temporal plane; 32-bit index math
 template <class T>
-__global__ void k_sweep(const T* __restrict__ in, T* __restrict__ out, int n_t, int d0, int d1, int d2,
-                        int ax, int out_len, const int* __restrict__ ptr, const int* __restrict__ col,
-                        const T* __restrict__ w, const unsigned char* __restrict__ mask_in,
-                        const unsigned char* __restrict__ mask_out, int accumulate) {
-  int o0 = ax == 0 ? out_len : d0, o1 = ax == 1 ? out_len : d1, o2 = ax == 2 ? out_len : d2;
-  long long plane_out = (long long)o0 * o1 * o2;
-  long long plane_in = (long long)d0 * d1 * d2;
-  long long total = plane_out * n_t;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    long long t = idx / plane_out;
-    long long r = idx - t * plane_out;
-    int i0 = (int)(r % o0);
-    int i1 = (int)((r / o0) % o1);
-    int i2 = (int)(r / ((long long)o0 * o1));
-    int ia = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
-    T s = 0;
-    if (!mask_out || mask_out[r]) {
-      for (int k = ptr[ia]; k < ptr[ia + 1]; ++k) {
-        int c = col[k];
-        int j0 = ax == 0 ? c : i0, j1 = ax == 1 ? c : i1, j2 = ax == 2 ? c : i2;
-        long long sidx = ((long long)j2 * d1 + j1) * d0 + j0;
-        if (mask_in && !mask_in[sidx]) continue;
-        s += w[k] * in[t * plane_in + sidx];
-      }
+__global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __restrict__ out, int d0, int d1, int d2,
+                                               int ax, int o0, int o1, const int* __restrict__ ptr,
+                                               const int* __restrict__ col, const T* __restrict__ w,
+                                               const unsigned char* __restrict__ mask_in,
+                                               const unsigned char* __restrict__ mask_out, int accumulate) {
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= o0 * o1) return;
+  const int i0 = local % o0, i1 = local / o0, i2 = blockIdx.y, t = blockIdx.z;
+  const int o2 = gridDim.y;
+  const long long plane_out = (long long)o0 * o1 * o2;
+  const long long plane_in = (long long)d0 * d1 * d2;
+  const long long r = (long long)i2 * o0 * o1 + local;
+  const int ia = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
+  T s = 0;
+  if (!mask_out || mask_out[r]) {
+    const T* src = in + t * plane_in;
+    const int k1 = ptr[ia + 1];
+    for (int k = ptr[ia]; k < k1; ++k) {
+      const int c = col[k];
+      const int j0 = ax == 0 ? c : i0, j1 = ax == 1 ? c : i1, j2 = ax == 2 ? c : i2;
+      const long long sidx = ((long long)j2 * d1 + j1) * d0 + j0;
+      if (mask_in && !mask_in[sidx]) continue;
+      s += w[k] * src[sidx];
     }
-    if (accumulate) out[idx] += s;
-    else out[idx] = s;
   }
+  T* dst = out + t * plane_out + r;
+  if (accumulate) *dst += s;
+  else *dst = s;
 }
 
 }  // namespace
@@ -48,14 +48,13 @@ template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
              const int* col, const T* w, const unsigned char* mask_in, const unsigned char* mask_out,
              bool accumulate, hipStream_t s) {
-  long long o = (long long)(ax == 0 ? out_len : in_dims[0]) * (ax == 1 ? out_len : in_dims[1]) *
-                (ax == 2 ? out_len : in_dims[2]) * n_t;
-  if (o <= 0) return;
-  long long g = (o + 255) / 256;
-  if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_sweep<T>, dim3((unsigned)g), dim3(256), 0, s, in, out, n_t, in_dims[0],
-                     in_dims[1], in_dims[2], ax, out_len, ptr, col, w, mask_in, mask_out,
-                     accumulate ? 1 : 0);
+  const int o0 = ax == 0 ? out_len : in_dims[0], o1 = ax == 1 ? out_len : in_dims[1],
+            o2 = ax == 2 ? out_len : in_dims[2];
+  if ((long long)o0 * o1 * o2 * n_t <= 0) return;
+  if ((long long)o0 * o1 > (1LL << 30) || o2 > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the transfer kernel");
+  dim3 grid((unsigned)((o0 * o1 + 255) / 256), (unsigned)o2, (unsigned)n_t);
+  hipLaunchKernelGGL(k_sweep<T>, grid, dim3(256), 0, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax, o0, o1,
+                     ptr, col, w, mask_in, mask_out, accumulate ? 1 : 0);
   STMG_CHECK_LAUNCH();
 }
 
