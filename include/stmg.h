@@ -92,6 +92,10 @@ typedef struct {
                               removes more than 7/8 of ||w||; 1: always two passes */
   double rtol;             /* stop at ||b - S x||_2 / ||b||_2 <= rtol (true residual) */
   uint64_t seed;           /* reserved for randomised setup steps */
+  int32_t asm_variant;     /* 0: exact cell blocks, factored by generalised eigenvectors of the
+                              probed principal submatrices; 1: separable surrogate (fast
+                              diagonalisation, Cartesian meshes only) */
+  int32_t reserved1;
 } stmg_config;
 
 typedef struct {

@@ -150,6 +150,72 @@ def asm_blocks(op: spacetime.SlabOperator, S: sp.csr_matrix):
     return out
 
 
+def _assembled_1d(n_cells: int, p: int, h: float):
+    """Assembled 1D Q_p mass and stiffness matrices ((p+1)-point Gauss, GLL nodes) on a
+    uniform line of n_cells cells of length h (all nodes, no boundary condition)."""
+    xq, wq = basis.gauss(p + 1)
+    V, D = basis.lagrange(basis.gauss_lobatto(p + 1), xq)
+    Me = h * (V.T * wq) @ V
+    Ae = (D.T * wq) @ D / h
+    N = p * n_cells + 1
+    M = np.zeros((N, N))
+    A = np.zeros((N, N))
+    for c in range(n_cells):
+        sl = slice(c * p, c * p + p + 1)
+        M[sl, sl] += Me
+        A[sl, sl] += Ae
+    return M, A
+
+
+def fdm_blocks(op: spacetime.SlabOperator):
+    """Separable surrogate blocks of the additive Schwarz smoother (Cartesian levels only).
+
+    For cell K the spatial blocks are replaced by Kronecker products of per-axis principal
+    submatrices of the assembled 1D matrices on K's interior nodes,
+      M~ = M_z (x) M_y (x) M_x,   A~ = rho_K (A_z (x) M_y (x) M_x + M_z (x) A_y (x) M_x + M_z (x) M_y (x) A_x),
+    with rho_K the mean coefficient of the cell; the block is M_tau (x) A~ + Ntilde (x) M~ for
+    every time cell.  With a constant coefficient this is the exact principal block.
+    Returns (indices, inverse) pairs in the layout of asm_blocks."""
+    space, sl = op.space, op.slab
+    if space.verts is not None:
+        raise ValueError("the separable surrogate needs a Cartesian level")
+    d, p, r = space.dim, space.p, space.ratio
+    one_d = [_assembled_1d(space.cells[a], p, (space.hi[a] - space.lo[a]) / space.cells[a]) for a in range(d)]
+    coef = space.coef_fine.reshape(tuple(space.fine_cells[::-1]))
+    dofs = space.cell_dofs()
+    bm = op.bmask
+    nc = sl.nt_cell
+    c = sl.n_t // nc
+    Nx = space.n_x
+    out = []
+    for K, cc in enumerate(space.cell_coords()):
+        Ms, As = [], []
+        for a in range(d):
+            g0 = cc[a] * p
+            idx = [g0 + l for l in range(p + 1) if 0 < g0 + l < p * space.cells[a]]
+            M1, A1 = one_d[a]
+            Ms.append(M1[np.ix_(idx, idx)])
+            As.append(A1[np.ix_(idx, idx)])
+        box = tuple(slice(cc[a] * r, (cc[a] + 1) * r) for a in reversed(range(d)))
+        rho = float(np.mean(coef[box]))
+        if d == 2:
+            Mt = np.kron(Ms[1], Ms[0])
+            At = rho * (np.kron(As[1], Ms[0]) + np.kron(Ms[1], As[0]))
+        else:
+            Mt = np.kron(Ms[2], np.kron(Ms[1], Ms[0]))
+            At = rho * (np.kron(As[2], np.kron(Ms[1], Ms[0])) + np.kron(Ms[2], np.kron(As[1], Ms[0]))
+                        + np.kron(Ms[2], np.kron(Ms[1], As[0])))
+        sdofs = dofs[K][~bm[dofs[K]]]
+        if len(sdofs) == 0:
+            continue
+        B = np.kron(sl.M_tau, At) + np.kron(sl.N_tilde, Mt)
+        inv = np.linalg.inv(B)
+        for m in range(c):
+            idx = np.concatenate([(m * nc + i) * Nx + sdofs for i in range(nc)])
+            out.append((idx, inv))
+    return out
+
+
 def asm_apply(level: Level, r: np.ndarray) -> np.ndarray:
     """sum_T R_T^T S_TT^{-1} R_T r, plus the identity on Dirichlet DoFs."""
     r = r.ravel()
@@ -214,7 +280,8 @@ class Hierarchy:
     """Levels ordered coarsest (index 0) to finest (index L), as in Alg. stmg."""
 
     def __init__(self, fine_op: spacetime.SlabOperator, min_p: int = 1, coarse_cells: int = 2,
-                 omegas: Optional[List[float]] = None, n_smooth: int = 1, omega_rule: float = 0.0):
+                 omegas: Optional[List[float]] = None, n_smooth: int = 1, omega_rule: float = 0.0,
+                 asm_variant: int = 0):
         spaces = level_spaces(fine_op.space, min_p, coarse_cells)[::-1]
         self.n_smooth = n_smooth
         self.levels: List[Level] = []
@@ -224,7 +291,7 @@ class Hierarchy:
             if i == 0:
                 lev.lu = spla.splu(lev.S.tocsc())
             else:
-                lev.blocks = asm_blocks(op, lev.S)
+                lev.blocks = fdm_blocks(op) if asm_variant == 1 else asm_blocks(op, lev.S)
                 lev.P = prolongation(spaces[i - 1], space)
             self.levels.append(lev)
         for i, lev in enumerate(self.levels):

@@ -39,6 +39,7 @@ class CConfig(ctypes.Structure):
         ("vcycle_dtypes", ctypes.c_int32), ("omega", ctypes.c_double),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("gram_schmidt", ctypes.c_int32), ("rtol", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("asm_variant", ctypes.c_int32), ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -152,6 +153,7 @@ def c_config(cfg, **overrides) -> CConfig:
     c.hi[:] = [float(v) for v in (list(get("hi")) + [1, 1, 1])[:3]]
     c.vcycle_dtypes = int(overrides.get("vcycle_dtypes", 0))
     c.gram_schmidt = int(overrides.get("gram_schmidt", 0))
+    c.asm_variant = int(overrides.get("asm_variant", getattr(cfg, "asm_variant", 0)))
     c.omega = float(get("omega"))
     c.rtol = float(get("rtol"))
     c.seed = int(get("seed"))

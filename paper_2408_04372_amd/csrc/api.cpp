@@ -54,6 +54,7 @@ void check_config(const stmg_config* c) {
   if (c->precision < 0 || c->precision > 2) fail(STMG_E_ARG, "precision must be 0, 1 or 2");
   if (c->restart < 1 || c->restart > 200) fail(STMG_E_ARG, "restart must be in 1..200");
   if (c->gram_schmidt != 0 && c->gram_schmidt != 1) fail(STMG_E_ARG, "gram_schmidt must be 0 or 1");
+  if (c->asm_variant != 0 && c->asm_variant != 1) fail(STMG_E_ARG, "asm_variant must be 0 or 1");
   if (c->max_iter < 1) fail(STMG_E_ARG, "max_iter must be >= 1");
   if (!(c->rtol > 0.0)) fail(STMG_E_ARG, "rtol must be positive");
   if (c->vcycle_dtypes < 0 || c->vcycle_dtypes > 3) fail(STMG_E_ARG, "vcycle_dtypes must be in 0..3");
@@ -123,6 +124,8 @@ stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const do
     if (!out) stmg::fail(STMG_E_ARG, "out is NULL");
     check_config(cfg);
     if (vertices) check_vertices(cfg, vertices);
+    if (vertices && cfg->asm_variant == 1)
+      stmg::fail(STMG_E_UNSUPPORTED, "the separable smoother (asm_variant 1) needs a Cartesian mesh");
     auto t0 = std::chrono::steady_clock::now();
     int64_t bytes0 = stmg::DevBuf::total_bytes();
     std::unique_ptr<stmg_handle> h(new stmg_handle());

@@ -25,6 +25,8 @@ struct LevelData {            // precision-dependent data of one level
   DevBuf u, r, f, tmpA, tmpB; // V-cycle work vectors
   DevBuf Cinv;                // coarsest level only: dense inverse on interior DoFs
   DevBuf cellbuf;             // per-cell contributions (levels with few cells, see st_apply)
+  DevBuf fq, fl, frho, ftm;   // separable smoother: 1D eigenvectors / eigenvalues per axis and
+                              // boundary case, cell-mean coefficient, temporal blocks M_tau, N~
 };
 
 struct Level {
@@ -45,6 +47,7 @@ struct Level {
   LevelData<double> d64;
   LevelData<float> d32;
   bool has64 = false, has32 = false;
+  std::vector<double> rho_mean;   // cell mean of the finest coefficient (separable smoother)
   long long nst(int n_t) const { return g.nx * n_t; }
 };
 

@@ -129,6 +129,9 @@ void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {
 }
 
 // 1D prolongation from a coarse (pc, ncc cells) to a fine (pf, ncf cells) lattice along one axis
+// The transfers act on interior nodes only (P_full = M_f P M_c with the interior indicators
+// M); the indicator of a tensor lattice is the product of per-axis indicators, so it is
+// folded into the 1D factors: first and last rows and columns are dropped.
 void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R, hipStream_t s) {
   int r = ncf / ncc;
   int Nf = pf * ncf + 1, Nc = pc * ncc + 1;
@@ -141,9 +144,12 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
     double xi = ((cf - cc * r) + fn[lf]) / r;
     hm::Mat V, D;
     hm::lagrange(cn, hm::Vec{xi}, V, D);
+    if (g == 0 || g == Nf - 1) continue;                 // Dirichlet fine node
     for (int j = 0; j <= pc; ++j) {
       double w = V(0, j);
       if (std::fabs(w) < 1e-14) continue;
+      const int c = cc * pc + j;
+      if (c == 0 || c == Nc - 1) continue;                // Dirichlet coarse node
       rows[g].push_back({cc * pc + j, w});
       cols[cc * pc + j].push_back({g, w});
     }
@@ -235,7 +241,68 @@ void level_coefficients(Level& L, const std::vector<double>& coef_fine, const in
 
 // principal blocks A_KK, M_KK by probing the matrix-free operator, then the generalised
 // eigenproblem A Q = M Q Lambda (rocSOLVER, batched) and the per-mode temporal inverses
+// separable smoother: per-axis 1D tables for the four boundary cases, cell-mean coefficient
+template <class T> static void upload_fdm(LevelData<T>& d, const std::vector<double>& q, const std::vector<double>& lam,
+                                          const std::vector<double>& rho, const std::vector<double>& tmat,
+                                          hipStream_t s) {
+  auto cv = [](const std::vector<double>& v) { return std::vector<T>(v.begin(), v.end()); };
+  d.fq = upload(cv(q), s);
+  d.fl = upload(cv(lam), s);
+  d.frho = upload(cv(rho), s);
+  d.ftm = upload(cv(tmat), s);
+}
+
+void setup_fdm(stmg_handle* h, Level& L) {
+  hipStream_t s = h->stream;
+  const int n = L.g.n, p = L.g.p, dim = L.g.dim;
+  hm::Vec xq, wq;
+  hm::gauss(n, xq, wq);
+  hm::Mat V, D;
+  hm::lagrange(hm::gauss_lobatto(n), xq, V, D);
+  std::vector<double> q((size_t)3 * 4 * n * n, 0.0), lam((size_t)3 * 4 * n, 0.0);
+  for (int a = 0; a < dim; ++a) {
+    const double hx = (h->cfg.hi[a] - h->cfg.lo[a]) / L.cells[a];
+    hm::Mat Me(n, n), Ae(n, n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double m = 0.0, k = 0.0;
+        for (int t = 0; t < n; ++t) {
+          m += wq[t] * V(t, i) * V(t, j);
+          k += wq[t] * D(t, i) * D(t, j);
+        }
+        Me(i, j) = hx * m;
+        Ae(i, j) = k / hx;
+      }
+    for (int bc = 0; bc < 4; ++bc) {
+      const bool lower = bc & 1, upper = bc & 2;
+      hm::Mat M1 = Me, A1 = Ae;
+      if (!lower) { M1(0, 0) += Me(p, p); A1(0, 0) += Ae(p, p); }
+      if (!upper) { M1(p, p) += Me(0, 0); A1(p, p) += Ae(0, 0); }
+      for (int e : {0, p}) {
+        if ((e == 0 && !lower) || (e == p && !upper)) continue;
+        for (int i = 0; i < n; ++i) { M1(e, i) = M1(i, e) = 0.0; A1(e, i) = A1(i, e) = 0.0; }
+        M1(e, e) = 1.0;
+        A1(e, e) = 1.0;
+      }
+      hm::Mat Q;
+      hm::Vec lm;
+      hm::sym_gen_eig(A1, M1, Q, lm);
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) q[(((size_t)a * 4 + bc) * n + r) * n + c] = Q(r, c);
+      for (int c = 0; c < n; ++c) lam[((size_t)a * 4 + bc) * n + c] = lm[c];
+    }
+  }
+  std::vector<double> tmat(h->tm.M_tau.a);
+  tmat.insert(tmat.end(), h->tm.N_tilde.a.begin(), h->tm.N_tilde.a.end());
+  if (L.has64) upload_fdm<double>(L.d64, q, lam, L.rho_mean, tmat, s);
+  if (L.has32) upload_fdm<float>(L.d32, q, lam, L.rho_mean, tmat, s);
+}
+
 void setup_smoother(stmg_handle* h, Level& L) {
+  if (h->cfg.asm_variant == 1) {
+    setup_fdm(h, L);
+    return;
+  }
   hipStream_t s = h->stream;
   const GeomDesc& g = L.g;
   const int ns = g.dim == 3 ? g.n * g.n * g.n : g.n * g.n;
@@ -423,6 +490,26 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
       L->g.verts = L->verts.as<double>();
     }
     level_coefficients(*L, coef, fine_cells, s);
+    if (cfg.asm_variant == 1) {
+      // cell mean of the finest coefficient over the ratio^d finest cells of each cell
+      const int r = L->ratio;
+      L->rho_mean.assign((size_t)L->g.ncells, 0.0);
+      for (long long c = 0; c < L->g.ncells; ++c) {
+        const int cx = (int)(c % L->cells[0]), cy = (int)((c / L->cells[0]) % L->cells[1]),
+                  cz = dim == 3 ? (int)(c / ((long long)L->cells[0] * L->cells[1])) : 0;
+        double sum = 0.0;
+        int cnt = 0;
+        for (int z = 0; z < (dim == 3 ? r : 1); ++z)
+          for (int y = 0; y < r; ++y)
+            for (int x = 0; x < r; ++x) {
+              const long long f = ((long long)(cz * (dim == 3 ? r : 1) + z) * fine_cells[1] + (cy * r + y)) *
+                                      fine_cells[0] + (cx * r + x);
+              sum += coef[f];
+              ++cnt;
+            }
+        L->rho_mean[c] = sum / cnt;
+      }
+    }
     boundary_lists(*L, s);
     L->has64 = h->want64;
     L->has32 = h->want32;
@@ -485,8 +572,13 @@ template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T*
   h->timer.mark(TB_SMOOTH, h->stream);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(1, h->stream);
-  asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
-               (T)L.omega, h->stream, d.cellbuf.template as<T>());
+  if (h->cfg.asm_variant == 1)
+    asm_apply_fdm<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
+                     d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream,
+                     d.cellbuf.template as<T>());
+  else
+    asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
+                 (T)L.omega, h->stream, d.cellbuf.template as<T>());
   if (fine) h->ktimer.end(h->stream);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)L.omega, r, (T)1, u, h->stream);
   h->timer.mark(TB_GMG, h->stream);
@@ -516,9 +608,7 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
     T* out = last ? fine : bufs[ax & 1];
     const Transfer1D& tr = F.P[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w,
-               ax == 0 ? C.mask.as<unsigned char>() : nullptr,
-               last ? F.mask.as<unsigned char>() : nullptr, last && accumulate, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, last && accumulate, s);
     dims[ax] = tr.len_out;
     in = out;
   }
@@ -539,9 +629,7 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
     T* out = last ? coarse : bufs[ax & 1];
     const Transfer1D& tr = F.R[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w,
-               ax == 0 ? F.mask.as<unsigned char>() : nullptr,
-               last ? C.mask.as<unsigned char>() : nullptr, false, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, false, s);
     dims[ax] = tr.len_out;
     in = out;
   }

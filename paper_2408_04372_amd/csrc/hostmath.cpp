@@ -26,6 +26,76 @@ Mat matmul(const Mat& A, const Mat& B) {
   return C;
 }
 
+void sym_gen_eig(const Mat& A, const Mat& M, Mat& Q, Vec& lam) {
+  const int n = A.r;
+  Mat L(n, n);
+  for (int j = 0; j < n; ++j) {
+    double d = M(j, j);
+    for (int k = 0; k < j; ++k) d -= L(j, k) * L(j, k);
+    if (!(d > 0.0)) fail(STMG_E_ARG, "mass matrix of the separable smoother is not positive definite");
+    L(j, j) = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = M(i, j);
+      for (int k = 0; k < j; ++k) v -= L(i, k) * L(j, k);
+      L(i, j) = v / L(j, j);
+    }
+  }
+  // C = L^{-1} A L^{-T}: Y = L^{-1} A (column by column), then C = L^{-1} Y^T
+  auto lsolve = [&](const Mat& B) {
+    Mat X(n, n);
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        double v = B(i, c);
+        for (int k = 0; k < i; ++k) v -= L(i, k) * X(k, c);
+        X(i, c) = v / L(i, i);
+      }
+    return X;
+  };
+  Mat Y = lsolve(A), Yt(n, n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Yt(i, j) = Y(j, i);
+  Mat C = lsolve(Yt), V(n, n);
+  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += C(i, j) * C(i, j);
+    if (off < 1e-30) break;
+    for (int pq = 0; pq < n * n; ++pq) {
+      int p = pq / n, q = pq % n;
+      if (q <= p || std::fabs(C(p, q)) < 1e-300) continue;
+      double th = (C(q, q) - C(p, p)) / (2.0 * C(p, q));
+      double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+      double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+      for (int k = 0; k < n; ++k) {        // C <- G^T C G, V <- V G
+        double a = C(k, p), b = C(k, q);
+        C(k, p) = c * a - sn * b;
+        C(k, q) = sn * a + c * b;
+      }
+      for (int k = 0; k < n; ++k) {
+        double a = C(p, k), b = C(q, k);
+        C(p, k) = c * a - sn * b;
+        C(q, k) = sn * a + c * b;
+      }
+      for (int k = 0; k < n; ++k) {
+        double a = V(k, p), b = V(k, q);
+        V(k, p) = c * a - sn * b;
+        V(k, q) = sn * a + c * b;
+      }
+    }
+  }
+  lam.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) lam[i] = C(i, i);
+  // Q = L^{-T} V
+  Q = Mat(n, n);
+  for (int c = 0; c < n; ++c)
+    for (int i = n - 1; i >= 0; --i) {
+      double v = V(i, c);
+      for (int k = i + 1; k < n; ++k) v -= L(k, i) * Q(k, c);
+      Q(i, c) = v / L(i, i);
+    }
+}
+
 Mat inverse(const Mat& A0) {
   int n = A0.r;
   Mat A = A0, I(n, n);

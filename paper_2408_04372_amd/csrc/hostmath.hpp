@@ -21,6 +21,9 @@ struct Mat {
 
 Mat matmul(const Mat& A, const Mat& B);
 Mat inverse(const Mat& A);            // Gauss-Jordan with partial pivoting; throws if singular
+// A Q = M Q diag(lam) with Q^T M Q = I, for symmetric A and symmetric positive definite M
+// (small n): Cholesky of M, then cyclic Jacobi rotations on L^{-1} A L^{-T}.
+void sym_gen_eig(const Mat& A, const Mat& M, Mat& Q, Vec& lam);
 
 // n-point Gauss-Legendre rule on [0, 1].
 void gauss(int n, Vec& x, Vec& w);

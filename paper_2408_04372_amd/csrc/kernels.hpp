@@ -67,12 +67,9 @@ template <class T> void norm2_check(const T* x, long long n, double* out, double
 // ---- transfers (transfer.hip) ---------------------------------------------------------------
 // One 1D sweep along axis `ax` of a [n_t][n2][n1][n0] array (x fastest):
 // out[.., i, ..] (+)= sum_{k in row i} w[k] * in[.., col[k], ..] with CSR (ptr, col, w).
-// mask_in / mask_out: optional per-node interior flags (1 byte per node of the input /
-// output lattice): masked-out entries read as zero / are written as zero.
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
-             const int* col, const T* w, const unsigned char* mask_in, const unsigned char* mask_out,
-             bool accumulate, hipStream_t s);
+             const int* col, const T* w, bool accumulate, hipStream_t s);
 
 // ---- smoother (asm.hip) ----------------------------------------------------------------------
 // Set-up: probe vectors (two planes) for colour `colour` (of 3^dim) and cell-local node b.
@@ -91,6 +88,14 @@ template <class Tout> void convert_from_double(const double* a, Tout* b, long lo
 template <class T>
 void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
                T omega, hipStream_t s, T* cellbuf = nullptr);
+
+// Separable (fast diagonalisation) variant on Cartesian levels:
+//   u += omega * sum_K R_K^T (I (x) Q) [rho_K lambda_s M_tau + N~]^{-1} (I (x) Q^T) R_K r,
+// Q = Q_z (x) Q_y (x) Q_x from per-axis 1D generalised eigenproblems (tables fq [3][4][n][n],
+// fl [3][4][n] by axis and boundary case), frho per cell, ftm = [M_tau; N~] (nt_cell^2 each).
+template <class T>
+void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T* fl, const T* frho,
+                   const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf = nullptr);
 
 // ---- coarse solve (coarse.hip) ---------------------------------------------------------------------
 // z[idx[i]] = sum_j Cinv[i][j] f[idx[j]] for the m interior DoFs of the coarsest level.

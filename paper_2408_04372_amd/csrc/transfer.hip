@@ -2,7 +2,7 @@
 // prolongation is a Kronecker product of 1D interpolation matrices
 // (P = P_z (x) P_y (x) P_x, applied to every temporal plane, "P^h (x) u"), so it is
 // applied as d one-dimensional sweeps; the restriction R = P^T uses the transposed
-// 1D matrices.  Each sweep is a banded 1D contraction with unit-stride access
+// 1D matrices.  Dirichlet rows and columns are already removed from the 1D factors.  Each sweep is a banded 1D contraction with unit-stride access
 // along x, so consecutive lanes read consecutive addresses in every direction.
 #include "kernels.hpp"
 
@@ -15,8 +15,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __restrict__ out, int d0, int d1, int d2,
                                                int ax, int o0, int o1, const int* __restrict__ ptr,
                                                const int* __restrict__ col, const T* __restrict__ w,
-                                               const unsigned char* __restrict__ mask_in,
-                                               const unsigned char* __restrict__ mask_out, int accumulate) {
+                                               int accumulate) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= o0 * o1) return;
   const int i0 = local % o0, i1 = local / o0, i2 = blockIdx.y, t = blockIdx.z;
@@ -26,16 +25,12 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __re
   const long long r = (long long)i2 * o0 * o1 + local;
   const int ia = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
   T s = 0;
-  if (!mask_out || mask_out[r]) {
-    const T* src = in + t * plane_in;
-    const int k1 = ptr[ia + 1];
-    for (int k = ptr[ia]; k < k1; ++k) {
-      const int c = col[k];
-      const int j0 = ax == 0 ? c : i0, j1 = ax == 1 ? c : i1, j2 = ax == 2 ? c : i2;
-      const long long sidx = ((long long)j2 * d1 + j1) * d0 + j0;
-      if (mask_in && !mask_in[sidx]) continue;
-      s += w[k] * src[sidx];
-    }
+  const T* src = in + t * plane_in;
+  const int k1 = ptr[ia + 1];
+  for (int k = ptr[ia]; k < k1; ++k) {
+    const int c = col[k];
+    const int j0 = ax == 0 ? c : i0, j1 = ax == 1 ? c : i1, j2 = ax == 2 ? c : i2;
+    s += w[k] * src[((long long)j2 * d1 + j1) * d0 + j0];
   }
   T* dst = out + t * plane_out + r;
   if (accumulate) *dst += s;
@@ -46,21 +41,20 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __re
 
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
-             const int* col, const T* w, const unsigned char* mask_in, const unsigned char* mask_out,
-             bool accumulate, hipStream_t s) {
+             const int* col, const T* w, bool accumulate, hipStream_t s) {
   const int o0 = ax == 0 ? out_len : in_dims[0], o1 = ax == 1 ? out_len : in_dims[1],
             o2 = ax == 2 ? out_len : in_dims[2];
   if ((long long)o0 * o1 * o2 * n_t <= 0) return;
   if ((long long)o0 * o1 > (1LL << 30) || o2 > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the transfer kernel");
   dim3 grid((unsigned)((o0 * o1 + 255) / 256), (unsigned)o2, (unsigned)n_t);
   hipLaunchKernelGGL(k_sweep<T>, grid, dim3(256), 0, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax, o0, o1,
-                     ptr, col, w, mask_in, mask_out, accumulate ? 1 : 0);
+                     ptr, col, w, accumulate ? 1 : 0);
   STMG_CHECK_LAUNCH();
 }
 
 template void sweep1d<double>(const double*, double*, int, const int*, int, int, const int*, const int*,
-                              const double*, const unsigned char*, const unsigned char*, bool, hipStream_t);
+                              const double*, bool, hipStream_t);
 template void sweep1d<float>(const float*, float*, int, const int*, int, int, const int*, const int*,
-                             const float*, const unsigned char*, const unsigned char*, bool, hipStream_t);
+                             const float*, bool, hipStream_t);
 
 }  // namespace stmg

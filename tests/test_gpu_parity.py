@@ -197,3 +197,62 @@ def test_wave_velocity_rejects_heat():
         U = torch.zeros(h.size(0), dtype=torch.float64, device=DEV)
         with pytest.raises(StmgError):
             h.wave_velocity(U, torch.empty_like(U))
+
+
+FDM_CASES = ["heat2d_q2_dg1", "wave2d_q3_dg2", "heat3d_q1_dg0", "wave3d_q3_cgp2_c4"]
+
+
+@pytest.mark.parametrize("name", FDM_CASES)
+def test_smoother_separable(name):
+    cfg, verts, coef = problem(name)
+    print(f"case {name}", flush=True)
+    op = oracle_op(cfg, verts, coef)
+    lev = mg.Level(op=op, S=op.matrix())
+    lev.blocks = mg.fdm_blocks(op)
+    rng = np.random.default_rng(15)
+    b = rng.standard_normal(lev.S.shape[0])
+    x0 = rng.standard_normal(lev.S.shape[0])
+    omega = 0.37
+    ref = mg.smooth(lev, b, x0, 2, omega=omega)
+    with _handle(cfg, verts, coef, omega=omega, asm_variant=1) as h:
+        for dt, tol in ((torch.float64, 1e-11), (torch.float32, 2e-4)):
+            x = _t(x0, dt)
+            h.smooth(_t(b, dt), x, steps=2, level=0)
+            err = rel_err(_np(x), ref)
+            print(dt, "separable smoother rel err", err)
+            assert err < tol, dt
+
+
+@pytest.mark.parametrize("name", FDM_CASES)
+def test_vcycle_and_solve_separable(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op, n_smooth=cfg.n_smooth, asm_variant=1, omega_rule=-1.0)
+    rng = np.random.default_rng(16)
+    r = rng.standard_normal(op.matrix().shape[0])
+    ref = H.vcycle(r)
+    b = si.random_slab_vector(cfg, 17)
+    xd = op.solve(b)
+    with _handle(cfg, verts, coef, omega=-1.0, asm_variant=1, rtol=1e-12, precision=0, max_iter=300) as h:
+        L = h.info["n_levels"]
+        got_omega = h.info["omega"][: L - 1]
+        assert np.allclose(got_omega, [H.levels[L - 1 - l].omega for l in range(L - 1)], rtol=1e-4)
+        for l in range(L - 1):
+            h.set_omega(l, H.levels[L - 1 - l].omega)
+        for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+            z = torch.empty(r.size, dtype=dt, device=DEV)
+            h.vcycle(_t(r, dt), z)
+            assert rel_err(_np(z), ref) < tol, dt
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        info = h.solve(_t(b).view(-1), x)
+        err = np.linalg.norm(_np(x) - xd.ravel()) / np.linalg.norm(xd)
+    print(name, info, "error", err)
+    assert info["rel_residual"] <= 1e-12
+    assert err < 1e-10
+
+
+def test_separable_rejects_perturbed_mesh():
+    from paper_2408_04372_amd import StmgError
+    cfg, verts, coef = problem("heat3d_q2_dg1_pert")
+    with pytest.raises(StmgError):
+        _handle(cfg, verts, coef, asm_variant=1)

@@ -120,3 +120,36 @@ def test_vcycle_is_linear_and_reduces_error():
     for _ in range(6):
         x = x + H.vcycle(b1.ravel() - op.apply(x))
     assert np.linalg.norm(x - xd) < 0.5 * e0
+
+
+def test_separable_blocks_exact_for_constant_coefficient():
+    # Cartesian mesh, constant coefficient: the assembled operator is a Kronecker product, so the
+    # separable surrogate is the exact principal block (Section 3.3 blocks, fast diagonalisation)
+    for cfg in [Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=2, n_cells=(3, 2, 3),
+                          tau=0.05, coef="one", seed=3),
+                Config(dim=2, problem=1, time_method=1, p=3, k=2, n_time_cells=2, n_cells=(3, 4, 1),
+                          tau=0.05, coef="one", seed=4)]:
+        verts, coef = draw_problem(cfg)
+        op = spacetime.from_config(cfg, verts, coef * 2.5)
+        exact = mg.asm_blocks(op, op.matrix())
+        fdm = mg.fdm_blocks(op)
+        assert len(exact) == len(fdm)
+        for (i1, b1), (i2, b2) in zip(exact, fdm):
+            assert np.array_equal(i1, i2)
+            assert np.allclose(b1, b2, rtol=1e-10, atol=1e-10 * np.abs(b1).max())
+
+
+def test_separable_blocks_use_cell_mean_coefficient():
+    # a variable coefficient changes the surrogate only through rho_K: scaling one cell's
+    # coefficient scales the spatial stiffness part of its block (checked on a 1-cell mesh)
+    cfg = Config(dim=3, problem=0, time_method=0, p=2, k=0, n_time_cells=1, n_cells=(1, 1, 1), tau=1.0,
+                    coef="one", seed=5)
+    verts, coef = draw_problem(cfg)
+    op1 = spacetime.from_config(cfg, verts, coef)
+    op3 = spacetime.from_config(cfg, verts, 3.0 * coef)
+    (i1, b1), = mg.fdm_blocks(op1)
+    (i3, b3), = mg.fdm_blocks(op3)
+    # dG(0): block = tau-mass term + (A_tau = 1) * M: B = M_tau A~ + N~ M~ with M_tau = tau = 1
+    B1, B3 = np.linalg.inv(b1), np.linalg.inv(b3)
+    Mt = op1.Mi.toarray()[np.ix_(i1, i1)]
+    assert np.allclose(B3 - Mt, 3.0 * (B1 - Mt), rtol=1e-10, atol=1e-12)
