@@ -167,6 +167,37 @@ def _assembled_1d(n_cells: int, p: int, h: float):
     return M, A
 
 
+def fdm_cell(space: spatial.Space, cc, one_d, coef) -> tuple:
+    """Separable surrogate (M~, A~) of cell cc on its interior nodes (see fdm_blocks)."""
+    d, p, r = space.dim, space.p, space.ratio
+    Ms, As = [], []
+    for a in range(d):
+        g0 = cc[a] * p
+        idx = [g0 + l for l in range(p + 1) if 0 < g0 + l < p * space.cells[a]]
+        M1, A1 = one_d[a]
+        Ms.append(M1[np.ix_(idx, idx)])
+        As.append(A1[np.ix_(idx, idx)])
+    box = tuple(slice(cc[a] * r, (cc[a] + 1) * r) for a in reversed(range(d)))
+    rho = float(np.mean(coef[box]))
+    if d == 2:
+        Mt = np.kron(Ms[1], Ms[0])
+        At = rho * (np.kron(As[1], Ms[0]) + np.kron(Ms[1], As[0]))
+    else:
+        Mt = np.kron(Ms[2], np.kron(Ms[1], Ms[0]))
+        At = rho * (np.kron(As[2], np.kron(Ms[1], Ms[0])) + np.kron(Ms[2], np.kron(As[1], Ms[0]))
+                    + np.kron(Ms[2], np.kron(Ms[1], As[0])))
+    return Mt, At
+
+
+def fdm_setup(space: spatial.Space):
+    """Per-axis assembled 1D matrices and the finest coefficient array of a Cartesian level."""
+    if space.verts is not None:
+        raise ValueError("the separable surrogate needs a Cartesian level")
+    one_d = [_assembled_1d(space.cells[a], space.p, (space.hi[a] - space.lo[a]) / space.cells[a])
+             for a in range(space.dim)]
+    return one_d, space.coef_fine.reshape(tuple(space.fine_cells[::-1]))
+
+
 def fdm_blocks(op: spacetime.SlabOperator):
     """Separable surrogate blocks of the additive Schwarz smoother (Cartesian levels only).
 
@@ -177,11 +208,7 @@ def fdm_blocks(op: spacetime.SlabOperator):
     every time cell.  With a constant coefficient this is the exact principal block.
     Returns (indices, inverse) pairs in the layout of asm_blocks."""
     space, sl = op.space, op.slab
-    if space.verts is not None:
-        raise ValueError("the separable surrogate needs a Cartesian level")
-    d, p, r = space.dim, space.p, space.ratio
-    one_d = [_assembled_1d(space.cells[a], p, (space.hi[a] - space.lo[a]) / space.cells[a]) for a in range(d)]
-    coef = space.coef_fine.reshape(tuple(space.fine_cells[::-1]))
+    one_d, coef = fdm_setup(space)
     dofs = space.cell_dofs()
     bm = op.bmask
     nc = sl.nt_cell
@@ -189,27 +216,11 @@ def fdm_blocks(op: spacetime.SlabOperator):
     Nx = space.n_x
     out = []
     for K, cc in enumerate(space.cell_coords()):
-        Ms, As = [], []
-        for a in range(d):
-            g0 = cc[a] * p
-            idx = [g0 + l for l in range(p + 1) if 0 < g0 + l < p * space.cells[a]]
-            M1, A1 = one_d[a]
-            Ms.append(M1[np.ix_(idx, idx)])
-            As.append(A1[np.ix_(idx, idx)])
-        box = tuple(slice(cc[a] * r, (cc[a] + 1) * r) for a in reversed(range(d)))
-        rho = float(np.mean(coef[box]))
-        if d == 2:
-            Mt = np.kron(Ms[1], Ms[0])
-            At = rho * (np.kron(As[1], Ms[0]) + np.kron(Ms[1], As[0]))
-        else:
-            Mt = np.kron(Ms[2], np.kron(Ms[1], Ms[0]))
-            At = rho * (np.kron(As[2], np.kron(Ms[1], Ms[0])) + np.kron(Ms[2], np.kron(As[1], Ms[0]))
-                        + np.kron(Ms[2], np.kron(Ms[1], As[0])))
         sdofs = dofs[K][~bm[dofs[K]]]
         if len(sdofs) == 0:
             continue
-        B = np.kron(sl.M_tau, At) + np.kron(sl.N_tilde, Mt)
-        inv = np.linalg.inv(B)
+        Mt, At = fdm_cell(space, cc, one_d, coef)
+        inv = np.linalg.inv(np.kron(sl.M_tau, At) + np.kron(sl.N_tilde, Mt))
         for m in range(c):
             idx = np.concatenate([(m * nc + i) * Nx + sdofs for i in range(nc)])
             out.append((idx, inv))

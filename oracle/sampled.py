@@ -24,7 +24,7 @@ from typing import Dict, Iterable, List, Tuple
 
 import numpy as np
 
-from . import spacetime, spatial, temporal
+from . import mg, spacetime, spatial, temporal
 
 
 class Sampler:
@@ -34,9 +34,37 @@ class Sampler:
         self.cfg = cfg
         self.space = spacetime.fine_space(cfg, verts, coef)
         self.slab = temporal.slab(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau, cfg.t0)
-        self.bmask = self.space.boundary_mask()
-        self.dofs = self.space.cell_dofs()
         self._cache: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
+        self._fdm = None
+
+    # node and cell numbering (computed per cell: the full tables would not fit at 10^8 nodes)
+    def is_boundary(self, g: int) -> bool:
+        return any(x == 0 or x == m - 1 for x, m in zip(self.node_coords(g), self.space.nodes))
+
+    def cell_nodes(self, K: int) -> np.ndarray:
+        """Global node index of each cell-local node (x fastest), like spatial.Space.cell_dofs."""
+        p, n, dim = self.space.p, self.space.p + 1, self.space.dim
+        cc = []
+        k = K
+        for m in self.space.cells:
+            cc.append(k % m)
+            k //= m
+        loc = np.indices((n,) * dim).reshape(dim, -1)[::-1]        # rows: lx, ly(, lz), x fastest
+        idx = np.zeros(loc.shape[1], dtype=np.int64)
+        stride = 1
+        for d in range(dim):
+            idx += (cc[d] * p + loc[d]) * stride
+            stride *= self.space.nodes[d]
+        return idx
+
+    def node_boundary(self, nodes: np.ndarray) -> np.ndarray:
+        out = np.zeros(len(nodes), dtype=bool)
+        rest = nodes.copy()
+        for m in self.space.nodes:
+            x = rest % m
+            rest //= m
+            out |= (x == 0) | (x == m - 1)
+        return out
 
     # lattice helpers -----------------------------------------------------------------------
     def node_coords(self, g: int) -> List[int]:
@@ -88,16 +116,17 @@ class Sampler:
         """(S x)[i, g] for each (i, g) in samples; x of shape (n_t, N_x)."""
         x = x.reshape(self.slab.n_t, self.space.n_x)
         out = np.zeros(len(samples))
+        self.matrices([K for _, g in samples if not self.is_boundary(g) for K in self.cells_of_node(g)])
         for s, (i, g) in enumerate(samples):
-            if self.bmask[g]:
+            if self.is_boundary(g):
                 out[s] = x[i, g]
                 continue
             val = 0.0
             cells = self.cells_of_node(g)
             for K, (Mk, Ak) in zip(cells, self.matrices(cells)):
-                d = self.dofs[K]
+                d = self.cell_nodes(K)
                 a = int(np.nonzero(d == g)[0][0])
-                xK = x[:, d] * (~self.bmask[d])[None, :]           # (n_t, n_s)
+                xK = x[:, d] * (~self.node_boundary(d))[None, :]   # (n_t, n_s)
                 Ax = xK @ Ak[a]                                     # (A_K x^j)_g for every j
                 Mx = xK @ Mk[a]
                 val += self.slab.M_T[i] @ Ax + self.slab.N_T[i] @ Mx
@@ -107,15 +136,15 @@ class Sampler:
     # sampled additive Schwarz step -----------------------------------------------------------
     def local_blocks(self, K: int):
         """Interior node list of K and (A_h)_KK, (M_h)_KK on it (principal submatrices)."""
-        dK = self.dofs[K]
-        inner = dK[~self.bmask[dK]]
+        dK = self.cell_nodes(K)
+        inner = dK[~self.node_boundary(dK)]
         pos = {int(g): t for t, g in enumerate(inner)}
         n = len(inner)
         A = np.zeros((n, n))
         M = np.zeros((n, n))
         nb = self.neighbours(K)
         for K2, (Mk, Ak) in zip(nb, self.matrices(nb)):
-            d2 = self.dofs[K2]
+            d2 = self.cell_nodes(K2)
             loc = np.array([pos.get(int(g), -1) for g in d2])
             sel = np.nonzero(loc >= 0)[0]
             if len(sel) == 0:
@@ -125,19 +154,37 @@ class Sampler:
             M[ix] += Mk[np.ix_(sel, sel)]
         return inner, A, M
 
-    def asm_entries(self, r: np.ndarray, omega: float, samples) -> np.ndarray:
-        """u[i, g] after one additive Schwarz step u = omega * ASM(r) from u = 0."""
+    def separable_blocks(self, K: int):
+        """Interior node list of K and the separable surrogate (A~, M~) (oracle.mg.fdm_cell)."""
+        if self._fdm is None:
+            self._fdm = mg.fdm_setup(self.space)
+        dK = self.cell_nodes(K)
+        inner = dK[~self.node_boundary(dK)]
+        cc = []
+        k = K
+        for m in self.space.cells:
+            cc.append(k % m)
+            k //= m
+        Mt, At = mg.fdm_cell(self.space, cc, *self._fdm)
+        return inner, At, Mt
+
+    def asm_entries(self, r: np.ndarray, omega: float, samples, separable: bool = False) -> np.ndarray:
+        """u[i, g] after one additive Schwarz step u = omega * ASM(r) from u = 0 (exact cell
+        blocks, or the separable surrogate blocks of oracle.mg.fdm_blocks)."""
         r = r.reshape(self.slab.n_t, self.space.n_x)
         nc = self.slab.nt_cell
         out = np.zeros(len(samples))
+        if not separable:
+            self.matrices([K2 for _, g in samples if not self.is_boundary(g) for K in self.cells_of_node(g)
+                           for K2 in self.neighbours(K)])
         for s, (i, g) in enumerate(samples):
-            if self.bmask[g]:
+            if self.is_boundary(g):
                 out[s] = omega * r[i, g]
                 continue
             m, il = divmod(i, nc)
             val = 0.0
             for K in self.cells_of_node(g):
-                inner, A, M = self.local_blocks(K)
+                inner, A, M = self.local_blocks(K) if not separable else self.separable_blocks(K)
                 B = np.kron(self.slab.M_tau, A) + np.kron(self.slab.N_tilde, M)
                 rhs = r[m * nc:(m + 1) * nc][:, inner].ravel()          # [temporal][node]
                 sol = np.linalg.solve(B, rhs).reshape(nc, len(inner))

@@ -332,23 +332,24 @@ void setup_smoother(stmg_handle* h, Level& L) {
     }
   x2.release();
   y2.release();
-  DevBuf lam(sizeof(double) * g.ncells * ns), E(sizeof(double) * g.ncells * ns),
-      info(sizeof(int) * g.ncells);
+  DevBuf lam(sizeof(double) * g.ncells * ns), info(sizeof(int) * g.ncells);
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) fail(STMG_E_HIP, "rocblas_create_handle failed");
   rocblas_set_stream(rb, s);
-  rocblas_status st = rocsolver_dsygvd_strided_batched(
+  // Jacobi-based batched solver: the many small problems of one level are solved in one
+  // pass each sweep (the tridiagonal route spends most of its time forming eigenvectors)
+  DevBuf resid(sizeof(double) * g.ncells), sweeps(sizeof(int) * g.ncells);
+  rocblas_status st = rocsolver_dsygvj_strided_batched(
       rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, A.as<double>(), ns,
-      (rocblas_stride)ns * ns, M.as<double>(), ns, (rocblas_stride)ns * ns, lam.as<double>(), ns,
-      E.as<double>(), ns, info.as<int>(), (int)g.ncells);
+      (rocblas_stride)ns * ns, M.as<double>(), ns, (rocblas_stride)ns * ns, 0.0, resid.as<double>(), 100,
+      sweeps.as<int>(), lam.as<double>(), ns, info.as<int>(), (int)g.ncells);
   STMG_HIP(hipStreamSynchronize(s));
   rocblas_destroy_handle(rb);
-  if (st != rocblas_status_success) fail(STMG_E_HIP, "rocsolver_dsygvd_strided_batched failed");
+  if (st != rocblas_status_success) fail(STMG_E_HIP, "rocsolver_dsygvj_strided_batched failed");
   std::vector<int> inf = download<int>(info.get(), g.ncells, s);
   for (long long c = 0; c < g.ncells; ++c)
     if (inf[c] != 0) fail(STMG_E_ARG, "local smoother block is not positive definite (cell " + std::to_string(c) + ")");
   M.release();
-  E.release();
   int nt = h->tm.nt_cell;
   DevBuf Mt = upload(h->tm.M_tau.a, s), Nt = upload(h->tm.N_tilde.a, s), bad(sizeof(int));
   STMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));

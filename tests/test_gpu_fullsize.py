@@ -1,7 +1,10 @@
-"""Parity at the full benchmark size (heat 3D, 32^3 Q4 cells with perturbed vertices, dG(2),
-8 time cells: 51.5 M space-time DoFs), in the launch configuration the benchmark times.
+"""Parity at the full sizes of the five workloads, in their launch configurations:
+  heat 3D 32^3 Q4 perturbed dG(2) c=8 (51.5 M DoFs, the benchmark: FP64 V-cycle, exact cell blocks),
+  wave 3D 64^3 Q3 cGP(2) c=4 (57.5 M DoFs, FP32 V-cycle, exact cell blocks),
+  heat 3D 128^3 Q4 dG(1) c=2 (540 M DoFs, FP32 V-cycle, separable cell blocks, restart 10),
+  heat 3D 64^3 Q2 dG(1) c=4 (17.2 M DoFs, FP32 V-cycle, exact cell blocks).
 
-The assembled oracle does not fit at this size, so the operator and one smoother step are
+The assembled oracle does not fit at these sizes, so the operator and one smoother step are
 compared on sampled entries computed one by one by the oracle (cell-local assembly of the
 same definitions), and the V-cycle and the solve are checked through properties that hold
 at any size: linearity and contraction of the V-cycle, and the true residual of the solve
@@ -17,20 +20,31 @@ from oracle import sampled
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-CFG = si.paper_config(2)
+
+# config index -> (handle settings, V-cycle dtype)
+LAUNCH = {
+    2: (dict(vcycle_dtypes=3, precision=0, restart=30, asm_variant=0), torch.float64),
+    3: (dict(vcycle_dtypes=2, precision=1, restart=30, asm_variant=0), torch.float32),
+    4: (dict(vcycle_dtypes=2, precision=1, restart=10, asm_variant=1), torch.float32),
+    5: (dict(vcycle_dtypes=2, precision=1, restart=30, asm_variant=0), torch.float32),
+}
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=[2, 3, 4, 5], ids=lambda i: f"config{i}")
+def setup(request):
     from paper_2408_04372_amd import Handle
-    verts, coef = si.draw_problem(CFG)
-    print("creating full-size handle", CFG.name, flush=True)
-    h = Handle(CFG, verts, coef, vcycle_dtypes=3, precision=0, rtol=1e-8, restart=30, max_iter=300,
-               omega=-1.0)
-    smp = sampled.Sampler(CFG, verts, coef)
-    pts = sampled.sample_points(CFG, 24, 4, seed=2024)
-    yield h, smp, pts
+    idx = request.param
+    cfg = si.paper_config(idx)
+    kw, vdt = LAUNCH[idx]
+    verts, coef = si.draw_problem(cfg)
+    print(f"creating full-size handle {cfg.name} ({cfg.n_st} DoFs)", flush=True)
+    h = Handle(cfg, verts, coef, rtol=1e-8, max_iter=300, omega=-1.0, **kw)
+    print("setup s", h.info["setup_seconds"], "device GB", h.info["device_bytes"] / 1e9, flush=True)
+    smp = sampled.Sampler(cfg, verts, coef)
+    pts = sampled.sample_points(cfg, 24, 4, seed=2024 + idx)
+    yield cfg, h, smp, pts, vdt, kw
     h.close()
+    torch.cuda.empty_cache()
 
 
 def _dev(a, dtype=torch.float64):
@@ -44,9 +58,9 @@ def _entries(t, pts, n_x):
 
 
 def test_operator_sampled_entries(setup):
-    h, smp, pts = setup
+    cfg, h, smp, pts, vdt, kw = setup
     n_x = smp.space.n_x
-    x = np.random.default_rng(1).standard_normal((CFG.n_t, n_x))
+    x = np.random.default_rng(1).standard_normal((cfg.n_t, n_x))
     ref = smp.operator_entries(x, pts)
     scale = np.abs(ref).max()
     for dt, tol in ((torch.float64, 1e-12), (torch.float32, 3e-5)):
@@ -54,32 +68,33 @@ def test_operator_sampled_entries(setup):
         yt = torch.empty_like(xt)
         h.vmult(xt, yt)
         got = _entries(yt, pts, n_x)
+        del xt, yt
         err = np.abs(got - ref).max() / scale
-        print(dt, "operator sampled max rel err", err, flush=True)
+        print(cfg.name, dt, "operator sampled max rel err", err, flush=True)
         assert err < tol
 
 
 def test_smoother_sampled_entries(setup):
-    h, smp, pts = setup
+    cfg, h, smp, pts, vdt, kw = setup
     n_x = smp.space.n_x
-    r = np.random.default_rng(2).standard_normal((CFG.n_t, n_x))
+    r = np.random.default_rng(2).standard_normal((cfg.n_t, n_x))
     omega = h.info["omega"][0]
-    ref = smp.asm_entries(r, omega, pts)
-    rt = _dev(r)
+    ref = smp.asm_entries(r, omega, pts, separable=kw["asm_variant"] == 1)
+    rt = _dev(r, vdt)
     u = torch.zeros_like(rt)
     h.smooth(rt, u, steps=1)
     got = _entries(u, pts, n_x)
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    print("smoother sampled max rel err", err, "omega", omega, flush=True)
-    assert err < 1e-10
+    print(cfg.name, "smoother sampled max rel err", err, "omega", omega, flush=True)
+    assert err < (1e-10 if vdt == torch.float64 else 2e-5)
 
 
 def test_vcycle_linear_and_contracting(setup):
-    h, smp, pts = setup
+    cfg, h, smp, pts, vdt, kw = setup
     n = h.size(0)
     g = torch.Generator(device="cpu").manual_seed(3)
-    r1 = torch.randn(n, generator=g, dtype=torch.float64).to(DEV)
-    r2 = torch.randn(n, generator=g, dtype=torch.float64).to(DEV)
+    r1 = torch.randn(n, generator=g, dtype=vdt).to(DEV)
+    r2 = torch.randn(n, generator=g, dtype=vdt).to(DEV)
     z1, z2, z3 = (torch.empty_like(r1) for _ in range(3))
     h.vcycle(r1, z1)
     h.vcycle(r2, z2)
@@ -88,24 +103,23 @@ def test_vcycle_linear_and_contracting(setup):
     Sz = torch.empty_like(r1)
     h.vmult(z1, Sz)
     contraction = (torch.linalg.norm(r1 - Sz) / torch.linalg.norm(r1)).item()
-    print("vcycle linearity", lin, "contraction", contraction, flush=True)
-    assert lin < 1e-12
-    assert contraction < 0.9
+    del r1, r2, z1, z2, z3, Sz
+    print(cfg.name, "vcycle linearity", lin, "contraction", contraction, flush=True)
+    assert lin < (1e-12 if vdt == torch.float64 else 1e-5)
+    assert contraction < 1.0
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_solve_true_residual(setup, precision):
-    h, smp, pts = setup
+def test_solve_true_residual(setup):
+    cfg, h, smp, pts, vdt, kw = setup
     n_x = smp.space.n_x
-    b = si.random_slab_vector(CFG, 1001)
+    b = si.random_slab_vector(cfg, 1001)
     bt = _dev(b)
     x = torch.zeros_like(bt)
-    h.set_precision(precision)
     info = h.solve(bt, x)
-    h.set_precision(0)
-    print("solve", precision, info, flush=True)
+    print(cfg.name, "solve", info, flush=True)
     assert info["rel_residual"] <= 1e-8
-    xs = x.cpu().numpy().reshape(CFG.n_t, n_x)
-    res = b.reshape(CFG.n_t, n_x)
+    xs = x.cpu().numpy().reshape(cfg.n_t, n_x)
+    del bt, x
+    res = b.reshape(cfg.n_t, n_x)
     rows = np.array([res[i, g] for i, g in pts]) - smp.operator_entries(xs, pts)
     assert np.abs(rows).max() <= 1e-8 * np.linalg.norm(b)

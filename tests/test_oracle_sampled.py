@@ -39,6 +39,27 @@ def test_sample_points_cover_node_kinds():
     cfg = CFGS[0]
     pts = sampled.sample_points(cfg, 40, 8, seed=1)
     smp = sampled.Sampler(cfg, *si.draw_problem(cfg))
-    counts = sorted({len(smp.cells_of_node(g)) for _, g in pts if not smp.bmask[g]})
+    counts = sorted({len(smp.cells_of_node(g)) for _, g in pts if not smp.is_boundary(g)})
     assert counts == [1, 2, 4, 8]
-    assert sum(smp.bmask[g] for _, g in pts) == 8
+    assert sum(smp.is_boundary(g) for _, g in pts) == 8
+    # per-cell numbering agrees with the full tables of spatial.Space
+    dofs = smp.space.cell_dofs()
+    bm = smp.space.boundary_mask()
+    for K in (0, 5, smp.space.n_cells - 1):
+        assert np.array_equal(smp.cell_nodes(K), dofs[K])
+        assert np.array_equal(smp.node_boundary(dofs[K]), bm[dofs[K]])
+
+
+def test_sampled_separable_step_matches_blocks():
+    cfg = si.Config(dim=3, problem=0, time_method=0, p=3, k=1, n_time_cells=2, n_cells=(3, 2, 4), tau=0.05,
+                    coef="lognormal", coef_sigma=1.0, seed=44)
+    verts, coef = si.draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    lev = mg.Level(op=op, S=op.matrix(), blocks=mg.fdm_blocks(op))
+    x = np.random.default_rng(9).standard_normal((cfg.n_t, op.n_x))
+    u = 0.4 * mg.asm_apply(lev, x.ravel()).reshape(cfg.n_t, op.n_x)
+    smp = sampled.Sampler(cfg, verts, coef)
+    pts = sampled.sample_points(cfg, 20, 4, seed=3)
+    got = smp.asm_entries(x, 0.4, pts, separable=True)
+    ref = np.array([u[i, g] for i, g in pts])
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max())
