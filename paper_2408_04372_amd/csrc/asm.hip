@@ -250,9 +250,9 @@ template <> struct Mma<float> {
 
 template <class T, int NT>
 __device__ inline void temporal_modes(T* P, int LD, const T* __restrict__ Tinv, long long cell, int ns,
-                                      int n_t, int tid) {
+                                      int n_t, int tid, int nthr) {
   const int c = n_t / NT;
-  for (int idx = tid; idx < c * ns; idx += 256) {
+  for (int idx = tid; idx < c * ns; idx += nthr) {
     int s = idx / c, m = idx - s * c;
     const T* Ti = Tinv + ((size_t)cell * ns + s) * NT * NT;
     T w[NT];
@@ -279,8 +279,11 @@ constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
 // (DIM, N) and the padded temporal width NTP are compile-time, so every index split is a
 // multiply-shift; each thread keeps one local node and walks the temporal planes, so the
 // node offset and its Dirichlet flag are computed once.
+// one wave per 16-row tile of Q (at least four waves): BT threads
+template <int NSP> constexpr int asm_threads() { return 64 * (NSP / 16 < 4 ? 4 : NSP / 16); }
+
 template <class T, int DIM, int N, int NTP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_asm_mfma(
+__global__ __launch_bounds__(512) void k_asm_mfma(
     GeomDesc g, ColourSet cs, int n_t, int nt_cell, const T* __restrict__ Q, const T* __restrict__ Tinv,
     const T* __restrict__ r, T* __restrict__ u, T omega, int nblocks, T* __restrict__ cellbuf) {
   typedef typename Mma<T>::v4 v4;
@@ -288,8 +291,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   constexpr int NSP = (NS + 15) / 16 * 16;
   constexpr int LD = NTP + 1;
   constexpr int MT = NSP / 16, NTt = NTP / 16, KS = NSP / 4;
-  constexpr int JSTEP = 256 / NSP;
-  static_assert(MT <= 4 * MAXM && NTt <= MAXNT && KS <= MAXK && 256 % NSP == 0, "cell too large");
+  constexpr int BT = asm_threads<NSP>();
+  constexpr int JSTEP = BT / NSP;
+  static_assert(MT <= 8 && NTt <= MAXNT && KS <= MAXK && BT % NSP == 0, "cell too large");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = reinterpret_cast<T*>(smem_raw);    // [NSP][LD]
   const long long li = xcd_swizzle(blockIdx.x, nblocks);
@@ -322,8 +326,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   v4 acc[MAXM][MAXNT];
   // W[s][j] = sum_a Q(a, s) R^T[a][j]
 #pragma unroll
-  for (int q = 0; q < MAXM; ++q) {
-    const int mt = wave + 4 * q;
+  for (int q = 0; q < 1; ++q) {
+    const int mt = wave;
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
     if (mt >= MT) continue;
@@ -344,8 +348,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < MAXM; ++q) {
-    const int mt = wave + 4 * q;
+  for (int q = 0; q < 1; ++q) {
+    const int mt = wave;
     if (mt >= MT) continue;
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt)
@@ -355,18 +359,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   __syncthreads();
   // per mode s and time cell m: W[s, m, :] <- (lambda_s M_tau + N~)^{-1} W[s, m, :]
   switch (nt_cell) {
-    case 1: temporal_modes<T, 1>(P, LD, Tinv, cell, NS, n_t, tid); break;
-    case 2: temporal_modes<T, 2>(P, LD, Tinv, cell, NS, n_t, tid); break;
-    case 3: temporal_modes<T, 3>(P, LD, Tinv, cell, NS, n_t, tid); break;
-    case 4: temporal_modes<T, 4>(P, LD, Tinv, cell, NS, n_t, tid); break;
-    case 5: temporal_modes<T, 5>(P, LD, Tinv, cell, NS, n_t, tid); break;
-    default: temporal_modes<T, 6>(P, LD, Tinv, cell, NS, n_t, tid); break;
+    case 1: temporal_modes<T, 1>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
+    case 2: temporal_modes<T, 2>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
+    case 3: temporal_modes<T, 3>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
+    case 4: temporal_modes<T, 4>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
+    case 5: temporal_modes<T, 5>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
+    default: temporal_modes<T, 6>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
   }
   __syncthreads();
   // Z[a][j] = sum_s Q(a, s) W[s][j]
 #pragma unroll
-  for (int q = 0; q < MAXM; ++q) {
-    const int mt = wave + 4 * q;
+  for (int q = 0; q < 1; ++q) {
+    const int mt = wave;
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
     if (mt >= MT) continue;
@@ -387,8 +391,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   __syncthreads();
   // Z into LDS, then added to the interior nodes
 #pragma unroll
-  for (int q = 0; q < MAXM; ++q) {
-    const int mt = wave + 4 * q;
+  for (int q = 0; q < 1; ++q) {
+    const int mt = wave;
     if (mt >= MT) continue;
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt)
@@ -413,7 +417,7 @@ void launch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cel
   constexpr int NS = DIM == 3 ? N * N * N : N * N;
   constexpr int NSP = (NS + 15) / 16 * 16;
   int nb = (int)cs.count;
-  hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(256), sizeof(T) * (size_t)NSP * (NTP + 1), s,
+  hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(asm_threads<NSP>()), sizeof(T) * (size_t)NSP * (NTP + 1), s,
                      g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, nb, cb);
 }
 

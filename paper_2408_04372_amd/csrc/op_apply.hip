@@ -244,16 +244,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     for (int s2 = 0; s2 < GS; ++s2) dst[s2] = (T)o[s2];
   }
   // stage every temporal plane of the cells (Dirichlet nodes read as zero), node index fastest
+  // (batches of UB loads are issued before their LDS stores, so the latencies overlap)
+  constexpr int UB = 24;
+  const int total = n_t * NQ;
   for (int lc = 0; lc < ncell; ++lc) {
     int cx, cy, cz;
     colour_cell(cs, g, li0 + lc, cx, cy, cz);
     T* dst = xs + (size_t)lc * n_t * NQ;
-    for (int idx = tid; idx < n_t * NQ; idx += nthr) {
-      int j = idx / NQ, node = idx - j * NQ;
-      int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
-      int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
-      bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 && gz != g.nn[2] - 1;
-      dst[idx] = in ? A.x[(long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx] : (T)0;
+    for (int base = tid; base < total; base += UB * nthr) {
+      T v[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = base + u * nthr;
+        v[u] = 0;
+        if (idx < total) {
+          const int j = idx / NQ, node = idx - j * NQ;
+          const int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
+          const int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+          const bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 &&
+                          gz != g.nn[2] - 1;
+          if (in) v[u] = A.x[(long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (base + u * nthr < total) dst[base + u * nthr] = v[u];
     }
   }
   __syncthreads();
@@ -374,12 +389,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     int cx, cy, cz;
     colour_cell(cs, g, li0 + lc2, cx, cy, cz);
     const T* src = xs + (size_t)lc2 * n_t * NQ;
-    for (int idx = tid; idx < n_t * NQ; idx += nthr) {
-      int j = idx / NQ, node = idx - j * NQ;
-      int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
-      int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
-      bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 && gz != g.nn[2] - 1;
-      if (in) A.y[(long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx] += A.scale * src[idx];
+    for (int base = tid; base < total; base += UB * nthr) {
+      long long addr[UB];
+      T v[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = base + u * nthr;
+        addr[u] = -1;
+        v[u] = 0;
+        if (idx < total) {
+          const int j = idx / NQ, node = idx - j * NQ;
+          const int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
+          const int gx = cx * p + lx, gy = cy * p + ly, gz = cz * p + lz;
+          const bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 &&
+                          gz != g.nn[2] - 1;
+          if (in) {
+            addr[u] = (long long)j * plane + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
+            v[u] = A.y[addr[u]];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (addr[u] >= 0) A.y[addr[u]] = v[u] + A.scale * src[base + u * nthr];
     }
   }
 }
