@@ -190,6 +190,22 @@ stmg_status stmg_kernel_stats_get(stmg_handle* h, stmg_kernel_stats* out, int re
  * V-cycle data must have been built (vcycle_dtypes). */
 stmg_status stmg_set_precision(stmg_handle* h, int precision);
 
+/* Slab right-hand side (Sections 2.1-2.2; eqs. heat-cg-dg-at-once, heat-cg-cg-at-once,
+ * wave-cg-dg-at-once, wave-cg-cg-at-once) with the coupling to the previous slab:
+ *   heat dG : b = (M_T (x) I) F + (a (x) M_h) u0
+ *   heat cGP: b = (M_T (x) I) F + (e_1 (x) beta) (x) F0 - (a (x) M_h + (e_1 (x) beta) (x) A_h) u0
+ *   wave dG : b = (M_T (x) I) F + (a (x) M_h) v0 + (A_T M_T^{-1} a (x) M_h) u0
+ *   wave cGP: b = (M_T (x) I) F + (e_1 (x) beta) (x) F0 - (a (x) M_h) v0 - ((e_1 (x) beta) (x) A_h) u0
+ *             - (A_T M_T^{-1} a (x) M_h) u0 + (A_T M_T^{-1} (e_1 (x) beta) (x) M_h) v0
+ * with a = e_1 (x) alpha (first time cell), A_h and M_h restricted to interior nodes, and b = 0
+ * on Dirichlet nodes.  F: device FP64 [n_t][N_x] loads (f(., t_i), phi) at the temporal DoF
+ * times (NULL reads as zero); F0: device FP64 [N_x] load at the slab start (cGP only);
+ * u0, v0: device FP64 [N_x] displacement and velocity at the slab start (NULL reads as zero;
+ * v0 is used by the wave problem only).  b: device FP64 [n_t][N_x], must not alias F.
+ * Asynchronous on the handle's stream. */
+stmg_status stmg_slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u0, const double* v0,
+                          double* b);
+
 /* Velocity of the wave slab from its displacement (Sections 2.1.2 and 2.2.2, eqs.
  * wave-cg-dg-ade and wave-cg-cg-ade; the second equation of the first-order system):
  *   dG(k):  V = M_T^{-1} (A_T U - a u0),    cGP(k): V = M_T^{-1} (A_T U + a u0 - b v0),

@@ -102,6 +102,8 @@ _SIGS = {
     "stmg_cnn_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "stmg_wave_velocity": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_void_p], ctypes.c_int),
+    "stmg_slab_rhs": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p], ctypes.c_int),
     "stmg_cnn_param_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
                             ctypes.c_int),
     "stmg_cnn_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -288,6 +290,21 @@ class Handle:
         th = np.empty(self.cnn_nparam, dtype=np.float32)
         _check(self.lib.stmg_cnn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p), th.size))
         return th
+
+    def slab_rhs(self, b, F=None, F0=None, u0=None, v0=None):
+        """b = slab right-hand side from loads F [n_t N_x] (and F0 [N_x] for cGP) and the
+        initial data u0, v0 [N_x] of the slab (None reads as zero)."""
+        import torch
+        self._sz(b, 0)
+        if F is not None:
+            self._sz(F, 0)
+        nx = self.info["n_x"][0]
+        for t in (F0, u0, v0):
+            if t is not None and (t.numel() != nx or t.dtype != torch.float64 or not t.is_contiguous()):
+                raise ValueError(f"plane data must be contiguous float64 with {nx} entries")
+        ptr = lambda t: _ptr(t, torch.float64) if t is not None else None
+        _check(self.lib.stmg_slab_rhs(self.h, ptr(F), ptr(F0), ptr(u0), ptr(v0), _ptr(b, torch.float64)))
+        return b
 
     def wave_velocity(self, U, V, u0=None, v0=None):
         """V = velocity of the wave slab from displacement U (u0, v0: initial data or None)."""

@@ -286,6 +286,17 @@ stmg_status stmg_cnn_get_params(stmg_handle* h, float* params, int64_t n) {
   });
 }
 
+stmg_status stmg_slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u0, const double* v0,
+                          double* b) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!b) stmg::fail(STMG_E_ARG, "b is NULL");
+    if ((const void*)b == (const void*)F) stmg::fail(STMG_E_ARG, "b must not alias F");
+    stmg::slab_rhs(h, F, F0, u0, v0, b);
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V) {
   return guarded([&]() -> stmg_status {
     level_of(h, 0);

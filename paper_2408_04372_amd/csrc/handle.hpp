@@ -106,6 +106,7 @@ struct stmg_handle {
   int64_t bytes_at_create = 0;
   stmg::CnnState* cnn = nullptr;
   stmg::DevBuf vel;            // wave velocity recovery: M_T^{-1} A_T and the u0 / v0 weights
+  stmg::DevBuf rhsc, rhs3x, rhs3y, rhs_mp, rhs_mc, rhs_mv, rhs_np, rhs_nc, rhs_nv;   // slab right-hand sides
   ~stmg_handle();
 };
 
@@ -120,6 +121,9 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
 void estimate_omegas(stmg_handle* h);
 stmg_status fgmres(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
 void wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V);
+void slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u0, const double* v0, double* b);
+// CSR of the nonzeros of a dense matrix (hierarchy.hip)
+template <class T> void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s);
 // learned stage (cnn.hip)
 void cnn_create(stmg_handle* h, int n_layers, const int* channels);
 long long cnn_param_count(stmg_handle* h);

@@ -103,6 +103,8 @@ LevelTables make_level_tables(int p) {
 
 namespace {
 
+}  // namespace
+
 // CSR of the nonzeros of a dense n x n matrix
 template <class T>
 void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s) {
@@ -118,6 +120,11 @@ void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStre
   col = upload(c, s);
   val = upload(v, s);
 }
+
+template void upload_csr<double>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
+template void upload_csr<float>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
+
+namespace {
 
 template <class T>
 void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {

@@ -256,3 +256,25 @@ def test_separable_rejects_perturbed_mesh():
     cfg, verts, coef = problem("heat3d_q2_dg1_pert")
     with pytest.raises(StmgError):
         _handle(cfg, verts, coef, asm_variant=1)
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat2d_q4_cgp2_pert", "wave2d_q3_dg2", "wave3d_q3_cgp2",
+                                  "wave3d_q2_cgp1_ragged"])
+def test_slab_rhs_matches_oracle(name):
+    from oracle import rhs
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    rng = np.random.default_rng(41)
+    F = rng.standard_normal((cfg.n_t, op.n_x))
+    F0, u0, v0 = (rng.standard_normal(op.n_x) for _ in range(3))
+    cgp = cfg.time_method == 1
+    ref = rhs.rhs(op, F, F0 if cgp else None, u0, v0)
+    ref_f = rhs.rhs(op, F, F0 if cgp else None)
+    with _handle(cfg, verts, coef) as h:
+        b = torch.empty(F.size, dtype=torch.float64, device=DEV)
+        h.slab_rhs(b, _t(F).view(-1), _t(F0) if cgp else None, _t(u0), _t(v0))
+        got = _np(b).reshape(ref.shape)
+        h.slab_rhs(b, _t(F).view(-1), _t(F0) if cgp else None)
+        got_f = _np(b).reshape(ref.shape)
+    assert rel_err(got, ref) < 1e-12
+    assert rel_err(got_f, ref_f) < 1e-12
