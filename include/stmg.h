@@ -206,6 +206,19 @@ stmg_status stmg_set_precision(stmg_handle* h, int precision);
 stmg_status stmg_slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u0, const double* v0,
                           double* b);
 
+/* Coordinates of the finest-level lattice nodes (Gauss-Lobatto nodes of every cell of a
+ * Cartesian mesh): xyz host [N_x][dim], x fastest like the vectors; for setting initial
+ * data by nodal interpolation.  STMG_E_UNSUPPORTED on meshes with displaced vertices. */
+stmg_status stmg_node_coordinates(stmg_handle* h, double* xyz);
+
+/* Point values of the Q_p interpolant of the first n_planes temporal planes of U (device
+ * FP64 [n_t][N_x], finest level) at npts points pts (host [npts][dim]); out: host
+ * [n_planes][npts].  Used for point goal quantities (Section 4.2).  Synchronises.
+ * STMG_E_ARG for points outside the domain or n_planes outside 1..n_t; STMG_E_UNSUPPORTED on
+ * meshes with displaced vertices. */
+stmg_status stmg_point_values(stmg_handle* h, const double* U, int n_planes, int npts, const double* pts,
+                              double* out);
+
 /* Velocity of the wave slab from its displacement (Sections 2.1.2 and 2.2.2, eqs.
  * wave-cg-dg-ade and wave-cg-cg-ade; the second equation of the first-order system):
  *   dG(k):  V = M_T^{-1} (A_T U - a u0),    cGP(k): V = M_T^{-1} (A_T U + a u0 - b v0),

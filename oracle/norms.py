@@ -56,3 +56,34 @@ def l2l2_error(op: SlabOperator, U: np.ndarray, u_exact, k: int, u0=None) -> flo
 def wave_energy(op: SlabOperator, u: np.ndarray, v: np.ndarray) -> float:
     """E = (v^T M_h v + u^T A_h u) / 2 on interior couplings."""
     return 0.5 * float(v @ (op.Mi @ v) + u @ (op.Ai @ u))
+
+
+def point_values(space, u: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """Values of the Q_p field with nodal values u (N_x,) or (n_planes, N_x) at points (npts, dim)
+    of a Cartesian mesh (goal quantities of Section 4.2)."""
+    from . import basis
+    if space.verts is not None:
+        raise ValueError("Cartesian meshes only")
+    u2 = np.atleast_2d(u)
+    d, p = space.dim, space.p
+    nodes = basis.gauss_lobatto(p + 1)
+    dofs = space.cell_dofs()
+    out = np.zeros((u2.shape[0], len(pts)))
+    for q, x in enumerate(np.asarray(pts, dtype=float)):
+        cc, phis = [], []
+        for a in range(d):
+            hx = (space.hi[a] - space.lo[a]) / space.cells[a]
+            c = min(int(np.floor((x[a] - space.lo[a]) / hx)), space.cells[a] - 1)
+            xi = (x[a] - space.lo[a]) / hx - c
+            cc.append(c)
+            phis.append(basis.lagrange(nodes, np.array([xi]))[0][0])
+        w = phis[0]
+        for a in range(1, d):
+            w = np.kron(phis[a], w)                      # x fastest, like the cell's local nodes
+        K = 0
+        stride = 1
+        for a in range(d):
+            K += cc[a] * stride
+            stride *= space.cells[a]
+        out[:, q] = u2[:, dofs[K]] @ w
+    return out if u.ndim == 2 else out[0]

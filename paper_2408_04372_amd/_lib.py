@@ -104,6 +104,9 @@ _SIGS = {
                             ctypes.c_void_p], ctypes.c_int),
     "stmg_slab_rhs": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p], ctypes.c_int),
+    "stmg_node_coordinates": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "stmg_point_values": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                           ctypes.c_void_p], ctypes.c_int),
     "stmg_cnn_param_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
                             ctypes.c_int),
     "stmg_cnn_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -290,6 +293,24 @@ class Handle:
         th = np.empty(self.cnn_nparam, dtype=np.float32)
         _check(self.lib.stmg_cnn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p), th.size))
         return th
+
+    def node_coordinates(self) -> np.ndarray:
+        """Finest-level node coordinates, shape (N_x, dim) (Cartesian meshes)."""
+        nx = self.info["n_x"][0]
+        out = np.empty((nx, self.cfg.dim), dtype=np.float64)
+        _check(self.lib.stmg_node_coordinates(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def point_values(self, U, points, n_planes: int = None) -> np.ndarray:
+        """Values of the first n_planes temporal planes of U at points (npts, dim): (n_planes, npts)."""
+        import torch
+        self._sz(U, 0)
+        n_planes = self.info["n_t"] if n_planes is None else int(n_planes)
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        out = np.empty((n_planes, pts.shape[0]), dtype=np.float64)
+        _check(self.lib.stmg_point_values(self.h, _ptr(U, torch.float64), n_planes, pts.shape[0],
+                                          pts.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def slab_rhs(self, b, F=None, F0=None, u0=None, v0=None):
         """b = slab right-hand side from loads F [n_t N_x] (and F0 [N_x] for cGP) and the

@@ -297,6 +297,27 @@ stmg_status stmg_slab_rhs(stmg_handle* h, const double* F, const double* F0, con
   });
 }
 
+stmg_status stmg_node_coordinates(stmg_handle* h, double* xyz) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!xyz) stmg::fail(STMG_E_ARG, "xyz is NULL");
+    stmg::node_coordinates(h, xyz);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_point_values(stmg_handle* h, const double* U, int n_planes, int npts, const double* pts,
+                              double* out) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    if (!U || !pts || !out) stmg::fail(STMG_E_ARG, "NULL argument");
+    if (n_planes < 1 || n_planes > h->tm.n_t) stmg::fail(STMG_E_ARG, "n_planes must be in 1..n_t");
+    if (npts < 0) stmg::fail(STMG_E_ARG, "npts must be >= 0");
+    if (npts > 0) stmg::point_values(h, U, n_planes, npts, pts, out);
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V) {
   return guarded([&]() -> stmg_status {
     level_of(h, 0);

@@ -122,6 +122,8 @@ void estimate_omegas(stmg_handle* h);
 stmg_status fgmres(stmg_handle* h, const double* b, double* x, stmg_solve_info* info);
 void wave_velocity(stmg_handle* h, const double* U, const double* u0, const double* v0, double* V);
 void slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u0, const double* v0, double* b);
+void node_coordinates(stmg_handle* h, double* xyz);
+void point_values(stmg_handle* h, const double* U, int n_planes, int npts, const double* pts, double* out);
 // CSR of the nonzeros of a dense matrix (hierarchy.hip)
 template <class T> void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s);
 // learned stage (cnn.hip)

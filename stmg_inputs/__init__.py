@@ -48,7 +48,7 @@ class Config:
     seed: int = 1
     # input recipe (not part of the solver configuration)
     perturb: float = 0.0         # interior vertex displacement, fraction of h, uniform per component
-    coef: str = "one"            # "one" | "lognormal" | "lognormal_checker"
+    coef: str = "one"            # "one" | "lognormal" | "lognormal_checker" | "shm" | "shm_rough"
     coef_sigma: float = 0.0
     name: str = ""
 
@@ -146,6 +146,23 @@ def cell_coefficients(cfg: Config, rng: Optional[np.random.Generator] = None) ->
     shape = tuple(cfg.cells[::-1])
     if cfg.coef == "one":
         return np.ones(shape, dtype=np.float64).ravel()
+    if cfg.coef in ("shm", "shm_rough"):
+        # layered medium of the structural-health-monitoring example (Section 4.2, eq. rho),
+        # evaluated at cell centres; the layer interfaces y = 0.2, z = 0.2 lie on cell faces
+        # for 5 * 2^r cells on [-1, 1]; "shm_rough" multiplies by c ~ U[0.4, 1.6] drawn per
+        # cell of the 5 x 5 x 5 initial mesh
+        h = np.array(cfg.h)
+        idx = np.indices(shape)                          # (z, y, x) cell indices
+        yc = cfg.lo[1] + (idx[1] + 0.5) * h[1]
+        zc = cfg.lo[2] + (idx[0] + 0.5) * h[2]
+        val = np.where(yc < 0.2, 1.0, np.where(zc < 0.2, 9.0, 16.0))
+        if cfg.coef == "shm_rough":
+            if rng is None:
+                rng = _rng(cfg.seed)
+            c = rng.uniform(0.4, 1.6, size=(5, 5, 5))
+            sub = [np.minimum((idx[a] * 5) // shape[a], 4) for a in range(3)]
+            val = val * c[sub[0], sub[1], sub[2]]
+        return np.ascontiguousarray(val.ravel())
     if rng is None:
         rng = _rng(cfg.seed)
     g = rng.standard_normal(shape)
@@ -155,6 +172,29 @@ def cell_coefficients(cfg: Config, rng: Optional[np.random.Generator] = None) ->
         par = sum(i // 8 for i in idx) % 2
         val = val * np.where(par == 1, 100.0, 1.0)
     return np.ascontiguousarray(val.ravel())
+
+
+def shm_config(r: int = 3, p: int = 3, k: int = 2, n_time_cells: int = 4, rough: bool = False,
+               seed: int = 7) -> Config:
+    """Structural-health-monitoring wave example (Section 4.2) on [-1, 1]^3 with 5 * 2^r cells per
+    direction, cGP(k) in time with tau = h / 2 (the paper refines time once more than space),
+    homogeneous Dirichlet data (the paper does not state the boundary condition)."""
+    n = 5 * 2 ** r
+    h = 2.0 / n
+    return Config(dim=3, problem=WAVE, time_method=CGP, p=p, k=k, n_time_cells=n_time_cells,
+                  n_cells=(n, n, n), tau=h / 2, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0),
+                  coef="shm_rough" if rough else "shm", precision=PREC_FP32, seed=seed,
+                  name=f"shm_wave3d_{n}cube_Q{p}_cGP{k}_c{n_time_cells}" + ("_rough" if rough else ""))
+
+
+def shm_initial_values(xyz: np.ndarray, s: float = 0.01) -> np.ndarray:
+    """Initial displacement of the example (eq. initial-shm) at the given points (N, 3):
+    exp(-|x/s|^2) (1 - |x/s|^2) for |x/s| < 1, else 0."""
+    q = np.sum((np.asarray(xyz) / s) ** 2, axis=1)
+    return np.where(q < 1.0, np.exp(-q) * (1.0 - q), 0.0)
+
+
+SHM_POINTS = np.array([[0.75, 0.0, 0.0], [0.0, 0.0, 0.75], [0.75, 0.1, 0.75]])   # goal-quantity points
 
 
 def draw_problem(cfg: Config):

@@ -98,3 +98,17 @@ def test_coarse_coefficient_lookup():
     f = sp_.coef_fine.reshape(4, 4)
     assert np.allclose(got[0], [f[0, 0], f[0, 1], f[1, 0], f[1, 1]])
     assert np.allclose(got[3], [f[2, 2], f[2, 3], f[3, 2], f[3, 3]])
+
+
+def test_point_values_reproduce_polynomials():
+    # the Q_p interpolant of a polynomial of degree <= p in each variable is exact everywhere
+    from oracle import norms
+    from stmg_inputs import Config, draw_problem
+    cfg = Config(dim=3, p=2, n_cells=(3, 2, 4), lo=(-1.0, 0.0, 0.5), hi=(1.0, 1.0, 1.5))
+    verts, coef = draw_problem(cfg)
+    space = fine_space(cfg, verts, coef)
+    X = spatial.node_coordinates(space)
+    f = lambda P: (1 + P[:, 0] - 2 * P[:, 0] ** 2) * (0.5 + P[:, 1] ** 2) * (2 - P[:, 2] + P[:, 2] ** 2)
+    rng = np.random.default_rng(3)
+    pts = np.stack([rng.uniform(lo, hi, 20) for lo, hi in zip(cfg.lo, cfg.hi)], axis=1)
+    assert np.allclose(norms.point_values(space, f(X), pts), f(pts), rtol=1e-12, atol=1e-12)
