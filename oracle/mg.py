@@ -126,6 +126,7 @@ class Level:
     blocks: list = field(default_factory=list)       # (index array, dense inverse)
     omega: float = 1.0
     P: Optional[sp.csr_matrix] = None                # from the next coarser level to this one
+    Pt: Optional[np.ndarray] = None                  # temporal prolongation instead of P
     lu: object = None
 
 
@@ -292,18 +293,27 @@ class Hierarchy:
 
     def __init__(self, fine_op: spacetime.SlabOperator, min_p: int = 1, coarse_cells: int = 2,
                  omegas: Optional[List[float]] = None, n_smooth: int = 1, omega_rule: float = 0.0,
-                 asm_variant: int = 0):
+                 asm_variant: int = 0, time_mg: bool = False):
         spaces = level_spaces(fine_op.space, min_p, coarse_cells)[::-1]
+        # (space, slab) per level, coarsest first: with time_mg, temporal levels on the coarsest
+        # spatial mesh come below the spatial ones ("first in space, then in time")
+        pairs = [(sp, fine_op.slab) for sp in spaces]
+        if time_mg:
+            for sl in temporal.time_levels(fine_op.slab):
+                pairs.insert(0, (spaces[0], sl))
         self.n_smooth = n_smooth
         self.levels: List[Level] = []
-        for i, space in enumerate(spaces):
-            op = fine_op if i == len(spaces) - 1 else spacetime.build(space, fine_op.slab)
+        for i, (space, sl) in enumerate(pairs):
+            op = fine_op if i == len(pairs) - 1 else spacetime.build(space, sl)
             lev = Level(op=op, S=op.matrix())
             if i == 0:
                 lev.lu = spla.splu(lev.S.tocsc())
             else:
                 lev.blocks = fdm_blocks(op) if asm_variant == 1 else asm_blocks(op, lev.S)
-                lev.P = prolongation(spaces[i - 1], space)
+                if pairs[i - 1][1] is not sl:
+                    lev.Pt = temporal.prolongation(sl, pairs[i - 1][1])
+                else:
+                    lev.P = prolongation(pairs[i - 1][0], space)
             self.levels.append(lev)
         for i, lev in enumerate(self.levels):
             if i == 0:
@@ -321,7 +331,7 @@ class Hierarchy:
         """Level i-1 -> level i on interior nodes, applied to every temporal row."""
         lev, coarse = self.levels[i], self.levels[i - 1]
         E = ec.reshape(coarse.op.n_t, coarse.op.n_x) * (~coarse.op.bmask)[None, :]
-        out = (lev.P @ E.T).T
+        out = lev.Pt @ E if lev.Pt is not None else (lev.P @ E.T).T
         out[:, lev.op.bmask] = 0.0
         return out.ravel()
 
@@ -329,7 +339,7 @@ class Hierarchy:
         """Level i -> level i-1: the transpose of prolong."""
         lev, coarse = self.levels[i], self.levels[i - 1]
         R = r.reshape(lev.op.n_t, lev.op.n_x) * (~lev.op.bmask)[None, :]
-        out = (lev.P.T @ R.T).T
+        out = lev.Pt.T @ R if lev.Pt is not None else (lev.P.T @ R.T).T
         out[:, coarse.op.bmask] = 0.0
         return out.ravel()
 

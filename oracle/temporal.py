@@ -132,3 +132,56 @@ def amplification(problem: int, method: int, k: int, z: complex) -> complex:
         M, A, alpha, beta, _ = cgp_local(k, 1.0)
         U = np.linalg.solve(z * M + A, -(alpha + z * beta).astype(complex))
     return U[-1]
+
+
+def degree(s: Slab) -> int:
+    """Temporal degree k of a slab (dG: k + 1 DoFs per cell, cGP: k)."""
+    return s.nt_cell - 1 if s.method == DG else s.nt_cell
+
+
+def coarsen(s: Slab, kind: str) -> Slab:
+    """The next coarser temporal space: 'k' lowers the degree by one, 'tau' merges pairs of
+    time cells (Section 3.2, k- and tau-multigrid)."""
+    k, c = degree(s), s.n_t // s.nt_cell
+    if kind == "k":
+        return slab(s.problem, s.method, k - 1, c, s.tau, s.t0)
+    return slab(s.problem, s.method, k, c // 2, 2.0 * s.tau, s.t0)
+
+
+def time_levels(s: Slab) -> list:
+    """Temporal coarsening after the spatial levels: k down to its minimum (dG 0, cGP 1), then
+    halve the number of time cells while it is even.  Returns the coarser slabs in order."""
+    out = []
+    cur = s
+    kmin = 0 if s.method == DG else 1
+    while degree(cur) > kmin:
+        cur = coarsen(cur, "k")
+        out.append(cur)
+    while (cur.n_t // cur.nt_cell) % 2 == 0:
+        cur = coarsen(cur, "tau")
+        out.append(cur)
+    return out
+
+
+def prolongation(fine: Slab, coarse: Slab) -> np.ndarray:
+    """Temporal prolongation P (fine.n_t x coarse.n_t): at every fine temporal DoF time, the
+    value of the coarse trial function of each coarse DoF (the coarse space lies in the fine
+    one, so this is the embedding; the restriction is P^T).  cGP: the first trial node of
+    coarse cell M is the last DoF of cell M - 1; in cell 0 it is the slab's initial value, a
+    constrained DoF that carries no correction, so that column is absent."""
+    kc = degree(coarse)
+    ncc = coarse.nt_cell
+    cc = coarse.n_t // ncc
+    nodes = basis.gauss_radau_right(kc + 1) if coarse.method == DG else basis.gauss_lobatto(kc + 1)
+    P = np.zeros((fine.n_t, coarse.n_t))
+    for i, t in enumerate(fine.times):
+        s = (t - coarse.t0) / coarse.tau
+        M = min(max(int(np.ceil(s - 1e-12)) - 1, 0), cc - 1)
+        vals = basis.lagrange(nodes, np.array([s - M]))[0][0]
+        if coarse.method == DG:
+            P[i, M * ncc:(M + 1) * ncc] = vals
+        else:
+            P[i, M * ncc:(M + 1) * ncc] = vals[1:]
+            if M > 0:
+                P[i, M * ncc - 1] += vals[0]
+    return P

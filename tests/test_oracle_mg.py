@@ -153,3 +153,22 @@ def test_separable_blocks_use_cell_mean_coefficient():
     B1, B3 = np.linalg.inv(b1), np.linalg.inv(b3)
     Mt = op1.Mi.toarray()[np.ix_(i1, i1)]
     assert np.allclose(B3 - Mt, 3.0 * (B1 - Mt), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_time_multigrid_hierarchy_solves(method):
+    # spatial levels, then k- and tau-levels on the coarsest mesh (Section 3.2): the V-cycle
+    # as FGMRES preconditioner reaches the direct solve
+    cfg = Config(dim=2, problem=1, time_method=method, p=2, k=2, n_time_cells=4, n_cells=(4, 4, 1),
+                 tau=0.05, coef="lognormal", coef_sigma=0.5, seed=61)
+    verts, coef = draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    H = mg.Hierarchy(op, omega_rule=-1.0, time_mg=True)
+    kinds = [lev.Pt is not None for lev in H.levels[1:]]
+    assert any(kinds) and not all(kinds)
+    assert H.levels[0].op.slab.n_t < op.slab.n_t
+    b = random_slab_vector(cfg, 3).ravel()
+    S = op.matrix()
+    x, it, rel = krylov.fgmres(lambda v: S @ v, b, H.vcycle, rtol=1e-12, restart=40, max_iter=200)
+    assert rel <= 1e-12
+    assert np.linalg.norm(x - op.solve(b).ravel()) <= 1e-9 * np.linalg.norm(x)

@@ -116,3 +116,23 @@ def test_wave_slab_factor():
         s = slice(2 * m, 2 * m + 2)
         assert np.allclose(sl.N_T[s, s], loc, rtol=1e-12)
     assert np.allclose(np.triu(sl.N_T, 2), 0.0)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_temporal_prolongation_reproduces_coarse_functions(method):
+    # the embedding of the coarse temporal space: a polynomial of the coarse degree (vanishing at
+    # t0 for cGP, whose initial value is constrained) is reproduced exactly at the fine DoF times
+    s = temporal.slab(0, method, 3, 4, 0.2, t0=1.0)
+    g = lambda t: (t - 1.0) * (2.0 - 0.5 * (t - 1.0))          # degree 2, zero at t0
+    cur = s
+    for c in temporal.time_levels(s):
+        P = temporal.prolongation(cur, c)
+        if temporal.degree(c) >= 2:
+            assert np.allclose(P @ g(c.times), g(cur.times), atol=1e-12)
+        if temporal.degree(c) >= 1:
+            lin = lambda t: 3.0 * (t - 1.0)
+            assert np.allclose(P @ lin(c.times), lin(cur.times), atol=1e-12)
+        else:                                   # dG(0): piecewise constants
+            assert np.allclose(P @ np.ones(c.n_t), np.ones(cur.n_t), atol=1e-12)
+        cur = c
+    assert temporal.degree(cur) == (0 if method == 0 else 1) and cur.n_t // cur.nt_cell == 1
