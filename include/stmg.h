@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define STMG_ABI_VERSION 1
+#define STMG_ABI_VERSION 2
 
 typedef enum {
   STMG_OK = 0,
@@ -95,7 +95,11 @@ typedef struct {
   int32_t asm_variant;     /* 0: exact cell blocks, factored by generalised eigenvectors of the
                               probed principal submatrices; 1: separable surrogate (fast
                               diagonalisation, Cartesian meshes only) */
-  int32_t reserved1;
+  int32_t time_mg;         /* 0: spatial levels only; 1: below the coarsest spatial level, coarsen in
+                              time (Section 3.2): lower k by one per level to its minimum (dG 0,
+                              cGP 1), then merge pairs of time cells while their number is even;
+                              temporal prolongation = embedding of the coarse trial functions,
+                              restriction its transpose; needs n_t <= 32 */
 } stmg_config;
 
 typedef struct {
@@ -114,8 +118,8 @@ typedef struct {
 #define STMG_MAX_LEVELS 16
 typedef struct {
   int32_t n_levels;
-  int32_t n_t;
-  int32_t nt_cell;                          /* temporal DoFs per time cell */
+  int32_t n_t;                              /* finest level */
+  int32_t nt_cell;                          /* temporal DoFs per time cell, finest level */
   int32_t temporal_nnz;                     /* nonzeros of M_T plus nonzeros of N_T */
   int64_t n_x[STMG_MAX_LEVELS];             /* lattice nodes per level */
   int32_t p[STMG_MAX_LEVELS];
@@ -124,12 +128,15 @@ typedef struct {
   int64_t coarse_unknowns;                  /* interior unknowns of the coarsest level */
   int64_t device_bytes;                     /* library-owned device memory */
   double setup_seconds;
+  int32_t n_t_level[STMG_MAX_LEVELS];       /* temporal DoFs per level (differ with time_mg) */
+  int32_t nt_cell_level[STMG_MAX_LEVELS];   /* temporal DoFs per time cell, per level */
 } stmg_info;
 
 typedef struct stmg_handle stmg_handle;
 
 /* Build the level hierarchy, smoother factors, relaxation parameters and the
- * coarse-level inverse (Section 3; Alg. mg-sequence with spatial levels).
+ * coarse-level inverse (Section 3; Alg. mg-sequence: p- then h-levels, then,
+ * with time_mg, k- and tau-levels on the coarsest spatial mesh).
  * vertices: host, nullable.  NULL means a Cartesian box [lo, hi]; otherwise
  *   (n_cells+1)^dim vertex positions, x fastest, dim doubles each.  Cells must
  *   not be inverted (STMG_E_ARG otherwise).
@@ -156,8 +163,11 @@ stmg_status stmg_smooth(stmg_handle* h, int level, int dtype, const void* b, voi
 stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z);
 
 /* fine = P coarse: prolongation from level+1 to level (Section 3.2): the coarse
- * Q_p function evaluated at the fine nodes; Dirichlet values of coarse are
- * treated as zero and fine Dirichlet values are written as zero. */
+ * Q_p function evaluated at the fine nodes (P^h (x) I on every temporal plane),
+ * or, between two temporal levels, the coarse temporal trial functions at the
+ * fine temporal DoF times (I (x) P^tau, stmg_info.n_t_level gives the sizes);
+ * Dirichlet values of coarse are treated as zero and fine Dirichlet values are
+ * written as zero. */
 stmg_status stmg_prolongate(stmg_handle* h, int level, int dtype, const void* coarse, void* fine);
 
 /* coarse = P^T fine (Section 3.2, restriction = adjoint of prolongation) on

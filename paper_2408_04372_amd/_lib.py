@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstmg.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_LEVELS = 16
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 5: "E_NONFINITE",
@@ -39,7 +39,7 @@ class CConfig(ctypes.Structure):
         ("vcycle_dtypes", ctypes.c_int32), ("omega", ctypes.c_double),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("gram_schmidt", ctypes.c_int32), ("rtol", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("asm_variant", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("asm_variant", ctypes.c_int32), ("time_mg", ctypes.c_int32),
     ]
 
 
@@ -64,6 +64,7 @@ class Info(ctypes.Structure):
         ("cells", (ctypes.c_int32 * 3) * MAX_LEVELS), ("omega", ctypes.c_double * MAX_LEVELS),
         ("coarse_unknowns", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
         ("setup_seconds", ctypes.c_double),
+        ("n_t_level", ctypes.c_int32 * MAX_LEVELS), ("nt_cell_level", ctypes.c_int32 * MAX_LEVELS),
     ]
 
 
@@ -159,6 +160,7 @@ def c_config(cfg, **overrides) -> CConfig:
     c.vcycle_dtypes = int(overrides.get("vcycle_dtypes", 0))
     c.gram_schmidt = int(overrides.get("gram_schmidt", 0))
     c.asm_variant = int(overrides.get("asm_variant", getattr(cfg, "asm_variant", 0)))
+    c.time_mg = int(overrides.get("time_mg", 0))
     c.omega = float(get("omega"))
     c.rtol = float(get("rtol"))
     c.seed = int(get("seed"))
@@ -216,10 +218,12 @@ class Handle:
                 "n_x": [inf.n_x[i] for i in range(L)], "p": [inf.p[i] for i in range(L)],
                 "cells": [tuple(inf.cells[i][:]) for i in range(L)],
                 "omega": [inf.omega[i] for i in range(L)], "coarse_unknowns": inf.coarse_unknowns,
-                "device_bytes": inf.device_bytes, "setup_seconds": inf.setup_seconds}
+                "device_bytes": inf.device_bytes, "setup_seconds": inf.setup_seconds,
+                "n_t_level": [inf.n_t_level[i] for i in range(L)],
+                "nt_cell_level": [inf.nt_cell_level[i] for i in range(L)]}
 
     def size(self, level: int = 0) -> int:
-        return self.info["n_t"] * self.info["n_x"][level]
+        return self.info["n_t_level"][level] * self.info["n_x"][level]
 
     def _sz(self, t, level):
         if t.numel() != self.size(level):

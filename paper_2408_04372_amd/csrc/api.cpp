@@ -55,6 +55,7 @@ void check_config(const stmg_config* c) {
   if (c->restart < 1 || c->restart > 200) fail(STMG_E_ARG, "restart must be in 1..200");
   if (c->gram_schmidt != 0 && c->gram_schmidt != 1) fail(STMG_E_ARG, "gram_schmidt must be 0 or 1");
   if (c->asm_variant != 0 && c->asm_variant != 1) fail(STMG_E_ARG, "asm_variant must be 0 or 1");
+  if (c->time_mg != 0 && c->time_mg != 1) fail(STMG_E_ARG, "time_mg must be 0 or 1");
   if (c->max_iter < 1) fail(STMG_E_ARG, "max_iter must be >= 1");
   if (!(c->rtol > 0.0)) fail(STMG_E_ARG, "rtol must be positive");
   if (c->vcycle_dtypes < 0 || c->vcycle_dtypes > 3) fail(STMG_E_ARG, "vcycle_dtypes must be in 0..3");
@@ -387,6 +388,8 @@ stmg_status stmg_query(stmg_handle* h, stmg_info* info) {
       info->p[l] = L.p;
       for (int d = 0; d < 3; ++d) info->cells[l][d] = L.cells[d];
       info->omega[l] = L.omega;
+      info->n_t_level[l] = L.n_t();
+      info->nt_cell_level[l] = L.ts->tm.nt_cell;
     }
     info->coarse_unknowns = h->levels.back()->cm;
     info->device_bytes = h->bytes_at_create;

@@ -1,4 +1,4 @@
-// The library handle: level hierarchy (Section 3, Alg. mg-sequence with spatial
+// The library handle: level hierarchy (Section 3, Alg. mg-sequence with spatial and temporal
 // levels), per-precision V-cycle data, and the FP64 FGMRES workspace.
 #pragma once
 
@@ -29,6 +29,19 @@ struct LevelData {            // precision-dependent data of one level
                               // boundary case, cell-mean coefficient, temporal blocks M_tau, N~
 };
 
+template <class T>
+struct TemporalBufs {
+  DevBuf mptr, mcol, mval, nptr, ncol, nval;
+  TemporalDev<T> dev;
+};
+
+// temporal discretisation of a level (the finest one, or a k- / tau-coarsened one)
+struct TSet {
+  hm::Temporal tm;
+  TemporalBufs<double> tp64;
+  TemporalBufs<float> tp32;
+};
+
 struct Level {
   int p = 1;
   int cells[3] = {1, 1, 1};
@@ -48,14 +61,13 @@ struct Level {
   LevelData<float> d32;
   bool has64 = false, has32 = false;
   std::vector<double> rho_mean;   // cell mean of the finest coefficient (separable smoother)
+  const TSet* ts = nullptr;       // temporal discretisation of this level
+  int tkind = 0;                  // transfer to the next coarser level: 0 in space, 1 in time
+  DevBuf Pt64, Pt32;              // temporal prolongation (n_t of this level x n_t of the next)
+  int n_t() const { return ts->tm.n_t; }
   long long nst(int n_t) const { return g.nx * n_t; }
 };
 
-template <class T>
-struct TemporalBufs {
-  DevBuf mptr, mcol, mval, nptr, ncol, nval;
-  TemporalDev<T> dev;
-};
 
 struct Timer {               // event-based bucket timer for stmg_solve
   std::vector<hipEvent_t> ev;
@@ -92,9 +104,8 @@ struct stmg_handle {
   stmg_config cfg;
   hipStream_t stream = nullptr;
   int device = 0;
-  stmg::hm::Temporal tm;
-  stmg::TemporalBufs<double> tp64;
-  stmg::TemporalBufs<float> tp32;
+  stmg::hm::Temporal tm;                              // finest temporal discretisation
+  std::vector<std::unique_ptr<stmg::TSet>> tsets;     // [0]: finest, then the coarser ones
   std::vector<std::unique_ptr<stmg::Level>> levels;
   bool want64 = true, want32 = false;
   // FGMRES workspace (finest level)
@@ -135,5 +146,5 @@ double cnn_forward(stmg_handle* h, const double* r, double* z);
 void cnn_param_grad(stmg_handle* h, const double* r, const double* dz, float* host);
 double cnn_train_step(stmg_handle* h, const double* r, const double* e, double lr);
 template <class T> LevelData<T>& ldata(Level& L);
-template <class T> const TemporalDev<T>& tdev(stmg_handle* h);
+template <class T> const TemporalDev<T>& tdev(const Level& L);
 }  // namespace stmg

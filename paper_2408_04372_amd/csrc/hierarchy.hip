@@ -1,9 +1,11 @@
 // Level hierarchy, smoother set-up, relaxation estimates and the V-cycle
-// (Section 3: Alg. stmg and Alg. mg-sequence, spatial levels only).
+// (Section 3: Alg. stmg and Alg. mg-sequence).
 //
 // Level sequence (finest first): halve p while p > min_p, then halve the cell
 // count per direction while every direction stays even and does not drop below
-// coarse_cells.  Coarse h-levels take the even-index vertex subset and
+// coarse_cells; with time_mg, then lower the temporal degree k by one per level
+// to its minimum and halve the number of time cells while it is even, all on the
+// coarsest spatial mesh.  Coarse h-levels take the even-index vertex subset and
 // re-discretise; their coefficient at a quadrature point is that of the finest
 // descendant cell whose reference sub-box contains the point.
 #include <rocblas/rocblas.h>
@@ -20,8 +22,8 @@ namespace stmg {
 
 template <> LevelData<double>& ldata<double>(Level& L) { return L.d64; }
 template <> LevelData<float>& ldata<float>(Level& L) { return L.d32; }
-template <> const TemporalDev<double>& tdev<double>(stmg_handle* h) { return h->tp64.dev; }
-template <> const TemporalDev<float>& tdev<float>(stmg_handle* h) { return h->tp32.dev; }
+template <> const TemporalDev<double>& tdev<double>(const Level& L) { return L.ts->tp64.dev; }
+template <> const TemporalDev<float>& tdev<float>(const Level& L) { return L.ts->tp32.dev; }
 
 // ------------------------------------------------------------------ timer
 void Timer::mark(int t, hipStream_t s) {
@@ -299,8 +301,8 @@ void setup_fdm(stmg_handle* h, Level& L) {
       for (int c = 0; c < n; ++c) lam[((size_t)a * 4 + bc) * n + c] = lm[c];
     }
   }
-  std::vector<double> tmat(h->tm.M_tau.a);
-  tmat.insert(tmat.end(), h->tm.N_tilde.a.begin(), h->tm.N_tilde.a.end());
+  std::vector<double> tmat(L.ts->tm.M_tau.a);
+  tmat.insert(tmat.end(), L.ts->tm.N_tilde.a.begin(), L.ts->tm.N_tilde.a.end());
   if (L.has64) upload_fdm<double>(L.d64, q, lam, L.rho_mean, tmat, s);
   if (L.has32) upload_fdm<float>(L.d32, q, lam, L.rho_mean, tmat, s);
 }
@@ -357,8 +359,8 @@ void setup_smoother(stmg_handle* h, Level& L) {
   for (long long c = 0; c < g.ncells; ++c)
     if (inf[c] != 0) fail(STMG_E_ARG, "local smoother block is not positive definite (cell " + std::to_string(c) + ")");
   M.release();
-  int nt = h->tm.nt_cell;
-  DevBuf Mt = upload(h->tm.M_tau.a, s), Nt = upload(h->tm.N_tilde.a, s), bad(sizeof(int));
+  int nt = L.ts->tm.nt_cell;
+  DevBuf Mt = upload(L.ts->tm.M_tau.a, s), Nt = upload(L.ts->tm.N_tilde.a, s), bad(sizeof(int));
   STMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
   if (L.has32) {
     L.d32.Q.alloc(sizeof(float) * nblk);
@@ -397,7 +399,7 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
 // coarsest level: probe the interior operator column by column, invert on the host
 void setup_coarse(stmg_handle* h, Level& L) {
   hipStream_t s = h->stream;
-  int n_t = h->tm.n_t;
+  int n_t = L.n_t();
   std::vector<unsigned char> mask = download<unsigned char>(L.mask.get(), L.g.nx, s);
   std::vector<long long> idx;
   for (int t = 0; t < n_t; ++t)
@@ -416,7 +418,7 @@ void setup_coarse(stmg_handle* h, Level& L) {
     double one = 1.0, zero = 0.0;
     STMG_HIP(hipMemcpyAsync(x.as<double>() + idx[j], &one, sizeof(double), hipMemcpyHostToDevice, s));
     fill<double>(y.as<double>(), 0.0, n, s);
-    st_apply<double>(L.g, L.lt, h->tp64.dev, x.as<double>(), y.as<double>(), 1.0, s);
+    st_apply<double>(L.g, L.lt, tdev<double>(L), x.as<double>(), y.as<double>(), 1.0, s);
     std::vector<double> col = download<double>(y.get(), n, s);
     for (int i = 0; i < m; ++i) C(i, j) = col[idx[i]];
     STMG_HIP(hipMemcpyAsync(x.as<double>() + idx[j], &zero, sizeof(double), hipMemcpyHostToDevice, s));
@@ -437,9 +439,26 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
   const stmg_config& cfg = h->cfg;
   hipStream_t s = h->stream;
   int dim = cfg.dim;
-  h->tm = hm::temporal(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau);
-  make_temporal<double>(h->tm, h->tp64, s);
-  make_temporal<float>(h->tm, h->tp32, s);
+  // temporal discretisations: the finest, then (time_mg) k down to its minimum and tau doubled
+  // while the number of time cells stays even (Section 3.2, applied below the spatial levels)
+  {
+    int k = cfg.k, c = cfg.n_time_cells;
+    double tau = cfg.tau;
+    const int kmin = cfg.time_method == 0 ? 0 : 1;
+    for (;;) {
+      auto ts = std::make_unique<TSet>();
+      ts->tm = hm::temporal(cfg.problem, cfg.time_method, k, c, tau);
+      if (ts->tm.n_t > TT_MAX && cfg.time_mg) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for temporal multigrid");
+      make_temporal<double>(ts->tm, ts->tp64, s);
+      make_temporal<float>(ts->tm, ts->tp32, s);
+      h->tsets.push_back(std::move(ts));
+      if (!cfg.time_mg) break;
+      if (k > kmin) --k;
+      else if (c % 2 == 0) { c /= 2; tau *= 2.0; }
+      else break;
+    }
+    h->tm = h->tsets[0]->tm;
+  }
   int fine_cells[3] = {cfg.n_cells[0], cfg.n_cells[1], dim == 3 ? cfg.n_cells[2] : 1};
   long long ncf = (long long)fine_cells[0] * fine_cells[1] * fine_cells[2];
   std::vector<double> coef(ncf, 1.0);
@@ -450,9 +469,9 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     }
   }
   // level shapes
-  struct Shape { int p; int cells[3]; int ratio; };
+  struct Shape { int p; int cells[3]; int ratio; int t; };
   std::vector<Shape> shapes;
-  Shape cur{cfg.p, {fine_cells[0], fine_cells[1], fine_cells[2]}, 1};
+  Shape cur{cfg.p, {fine_cells[0], fine_cells[1], fine_cells[2]}, 1, 0};
   shapes.push_back(cur);
   while (cur.p > cfg.min_p) {
     cur.p = std::max(cfg.min_p, cur.p / 2);
@@ -467,6 +486,10 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     cur.ratio *= 2;
     shapes.push_back(cur);
   }
+  for (size_t t = 1; t < h->tsets.size(); ++t) {
+    cur.t = (int)t;
+    shapes.push_back(cur);
+  }
   if ((int)shapes.size() > STMG_MAX_LEVELS) fail(STMG_E_UNSUPPORTED, "too many levels");
   std::vector<double> verts_host;
   if (vertices) {
@@ -479,6 +502,7 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     L->p = shapes[l].p;
     for (int d = 0; d < 3; ++d) L->cells[d] = shapes[l].cells[d];
     L->ratio = shapes[l].ratio;
+    L->ts = h->tsets[shapes[l].t].get();
     init_geom(*L, dim, cfg);
     L->lt = make_level_tables(L->p);
     if (vertices) {
@@ -527,15 +551,22 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
   for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
     Level& F = *h->levels[l];
     Level& C = *h->levels[l + 1];
+    if (F.ts != C.ts) {
+      F.tkind = 1;
+      hm::Mat Pt = hm::temporal_prolongation(F.ts->tm, C.ts->tm);
+      F.Pt64 = upload(Pt.a, s);
+      std::vector<float> p32(Pt.a.begin(), Pt.a.end());
+      F.Pt32 = upload(p32, s);
+      continue;
+    }
     for (int d = 0; d < dim; ++d) transfer_1d(C.p, C.cells[d], F.p, F.cells[d], F.P[d], F.R[d], s);
   }
   // smoothers, work vectors, coarse inverse
-  int n_t = h->tm.n_t;
   for (size_t l = 0; l < h->levels.size(); ++l) {
     Level& L = *h->levels[l];
     bool coarsest = (l + 1 == h->levels.size());
-    if (L.has64) alloc_work<double>(L, n_t, coarsest);
-    if (L.has32) alloc_work<float>(L, n_t, coarsest);
+    if (L.has64) alloc_work<double>(L, L.n_t(), coarsest);
+    if (L.has32) alloc_work<float>(L, L.n_t(), coarsest);
     if (!coarsest) setup_smoother(h, L);
     else setup_coarse(h, L);
   }
@@ -554,24 +585,24 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
 template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
   Level& L = *h->levels[level];
   hipStream_t s = h->stream;
-  long long n = L.nst(h->tm.n_t);
+  long long n = L.nst(L.n_t());
   fill<T>(y, (T)0, n, s);
   if (level == 0) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(h), x, y, (T)1, s, ldata<T>(L).cellbuf.template as<T>());
+  st_apply<T>(L.g, L.lt, tdev<T>(L), x, y, (T)1, s, ldata<T>(L).cellbuf.template as<T>());
   if (level == 0) h->ktimer.end(s);
-  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)1, x, (T)0, y, s);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)1, x, (T)0, y, s);
 }
 
 // r = f - S u
 template <class T> static void residual(stmg_handle* h, Level& L, const T* f, const T* u, T* r) {
   hipStream_t s = h->stream;
-  long long n = L.nst(h->tm.n_t);
+  long long n = L.nst(L.n_t());
   copy<T>(f, r, n, s);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(h), u, r, (T)-1, s, ldata<T>(L).cellbuf.template as<T>());
+  st_apply<T>(L.g, L.lt, tdev<T>(L), u, r, (T)-1, s, ldata<T>(L).cellbuf.template as<T>());
   if (fine) h->ktimer.end(s);
-  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)-1, u, (T)1, r, s);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)-1, u, (T)1, r, s);
 }
 
 // u += omega * ASM(r)
@@ -581,14 +612,14 @@ template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T*
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(1, h->stream);
   if (h->cfg.asm_variant == 1)
-    asm_apply_fdm<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
+    asm_apply_fdm<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
                      d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream,
                      d.cellbuf.template as<T>());
   else
-    asm_apply<T>(L.g, h->tm.n_t, h->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
+    asm_apply<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
                  (T)L.omega, h->stream, d.cellbuf.template as<T>());
   if (fine) h->ktimer.end(h->stream);
-  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, h->tm.n_t, (T)L.omega, r, (T)1, u, h->stream);
+  boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)L.omega, r, (T)1, u, h->stream);
   h->timer.mark(TB_GMG, h->stream);
 }
 
@@ -606,7 +637,12 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
   Level& C = *h->levels[level + 1];
   LevelData<T>& d = ldata<T>(F);
   hipStream_t s = h->stream;
-  int n_t = h->tm.n_t;
+  if (F.tkind == 1) {
+    const T* P = std::is_same<T, double>::value ? (const T*)F.Pt64.get() : (const T*)F.Pt32.get();
+    time_transfer<T>(P, F.n_t(), C.n_t(), F.g.nx, F.mask.as<unsigned char>(), coarse, fine, accumulate ? 1 : 0, s);
+    return;
+  }
+  int n_t = F.n_t();
   int dim = F.g.dim;
   const T* in = coarse;
   int dims[3] = {C.g.nn[0], C.g.nn[1], C.g.nn[2]};
@@ -627,7 +663,12 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
   Level& C = *h->levels[level + 1];
   LevelData<T>& d = ldata<T>(F);
   hipStream_t s = h->stream;
-  int n_t = h->tm.n_t;
+  if (F.tkind == 1) {
+    const T* P = std::is_same<T, double>::value ? (const T*)F.Pt64.get() : (const T*)F.Pt32.get();
+    time_transfer<T>(P, F.n_t(), C.n_t(), F.g.nx, F.mask.as<unsigned char>(), fine, coarse, 2, s);
+    return;
+  }
+  int n_t = F.n_t();
   int dim = F.g.dim;
   const T* in = fine;
   int dims[3] = {F.g.nn[0], F.g.nn[1], F.g.nn[2]};
@@ -648,7 +689,7 @@ template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u) {
   Level& L = *h->levels[level];
   LevelData<T>& d = ldata<T>(L);
   hipStream_t s = h->stream;
-  int n_t = h->tm.n_t;
+  int n_t = L.n_t();
   long long n = L.nst(n_t);
   if (level + 1 == (int)h->levels.size()) {
     coarse_apply<T>(d.Cinv.template as<T>(), L.cidx.as<long long>(), L.cm, f, u, s);
@@ -749,10 +790,10 @@ std::vector<std::complex<double>> hessenberg_eigs(const hm::Mat& H0) {
 void estimate_omegas(stmg_handle* h) {
   hipStream_t s = h->stream;
   const int steps = 15;
-  int n_t = h->tm.n_t;
   DevBuf red(sizeof(double) * RED_BLOCKS * PS), dots(sizeof(double) * 64);
   for (size_t l = 0; l + 1 < h->levels.size(); ++l) {
     Level& L = *h->levels[l];
+    const int n_t = L.n_t();
     long long n = L.nst(n_t);
     DevBuf V(sizeof(double) * n * (steps + 1)), r(sizeof(double) * n), z(sizeof(double) * n);
     DevBuf r32, z32;

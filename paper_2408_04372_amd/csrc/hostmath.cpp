@@ -287,6 +287,9 @@ Temporal temporal(int problem, int method, int k, int c, double tau) {
   T.n_t = n;
   T.nt_cell = nc;
   T.c = c;
+  T.method = method;
+  T.k = k;
+  T.tau = tau;
   T.M_T = Mat(n, n);
   T.A_T = Mat(n, n);
   for (int m = 0; m < c; ++m)
@@ -310,6 +313,41 @@ Temporal temporal(int problem, int method, int k, int c, double tau) {
   for (double v : T.N_T.a) mx = std::fmax(mx, std::fabs(v));
   for (double& v : T.N_T.a) if (std::fabs(v) < 1e-15 * mx) v = 0.0;
   return T;
+}
+
+namespace {
+// local DoF positions in [0, 1] of one time cell: dG the k+1 right Radau nodes, cGP the last
+// k of the k+1 Gauss-Lobatto nodes
+Vec dof_positions(const Temporal& t) {
+  if (t.method == 0) return gauss_radau_right(t.k + 1);
+  Vec gl = gauss_lobatto(t.k + 1);
+  return Vec(gl.begin() + 1, gl.end());
+}
+}  // namespace
+
+Mat temporal_prolongation(const Temporal& fine, const Temporal& coarse) {
+  if (fine.method != coarse.method) fail(STMG_E_ARG, "temporal transfer between different methods");
+  const Vec fpos = dof_positions(fine);
+  const Vec cnodes = coarse.method == 0 ? gauss_radau_right(coarse.k + 1) : gauss_lobatto(coarse.k + 1);
+  const int ncc = coarse.nt_cell;
+  Mat P(fine.n_t, coarse.n_t);
+  for (int m = 0; m < fine.c; ++m)
+    for (int j = 0; j < fine.nt_cell; ++j) {
+      const int i = m * fine.nt_cell + j;
+      const double t = (m + fpos[j]) * fine.tau;          // time from the slab start
+      const double sc = t / coarse.tau;
+      int M = (int)std::ceil(sc - 1e-12) - 1;              // coarse cell (t_{M}, t_{M+1}]
+      M = std::min(std::max(M, 0), coarse.c - 1);
+      Mat V, D;
+      lagrange(cnodes, Vec{sc - M}, V, D);
+      if (coarse.method == 0) {
+        for (int b = 0; b < ncc; ++b) P(i, M * ncc + b) = V(0, b);
+      } else {
+        for (int b = 0; b < ncc; ++b) P(i, M * ncc + b) = V(0, b + 1);
+        if (M > 0) P(i, M * ncc - 1) += V(0, 0);
+      }
+    }
+  return P;
 }
 
 }  // namespace hm

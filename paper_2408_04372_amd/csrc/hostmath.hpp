@@ -37,12 +37,19 @@ void lagrange(const Vec& nodes, const Vec& x, Mat& val, Mat& der);
 // Slab-level temporal data (Sections 2.1-2.2).
 struct Temporal {
   int n_t = 0, nt_cell = 0, c = 0;
+  int method = 0, k = 0;
+  double tau = 0.0;
   Mat M_T, A_T, N_T;      // n_t x n_t
   Mat M_tau, N_tilde;     // diagonal blocks (ASM local temporal factors)
   Vec alpha, beta;        // coupling of the first time cell to u0 (alpha) and, for cGP, v0 / F0 (beta)
 };
 // problem: 0 heat, 1 wave; method: 0 dG, 1 cGP.
 Temporal temporal(int problem, int method, int k, int c, double tau);
+// Temporal prolongation (fine.n_t x coarse.n_t) between two discretisations of the same slab
+// whose coarse trial space lies in the fine one: entry (i, j) is coarse trial function j at
+// the time of fine DoF i.  cGP: the first Gauss-Lobatto node of coarse cell M is the last DoF
+// of cell M - 1 (in cell 0 it is the slab's initial value, which carries no correction).
+Mat temporal_prolongation(const Temporal& fine, const Temporal& coarse);
 
 }  // namespace hm
 }  // namespace stmg

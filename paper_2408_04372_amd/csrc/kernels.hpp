@@ -71,6 +71,14 @@ template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
              const int* col, const T* w, bool accumulate, hipStream_t s);
 
+// Temporal transfer on the interior nodes of one spatial lattice of nx nodes (transfer.hip):
+// mode 0: out = (P (x) I) in, 1: out += (P (x) I) in, 2: out = (P^T (x) I) in, with P the dense
+// (nf x nc) temporal prolongation; vectors are [plane][node], Dirichlet nodes give zero.
+constexpr int TT_MAX = 32;
+template <class T>
+void time_transfer(const T* P, int nf, int nc, long long nx, const unsigned char* mask, const T* in, T* out,
+                   int mode, hipStream_t s);
+
 // ---- smoother (asm.hip) ----------------------------------------------------------------------
 // Set-up: probe vectors (two planes) for colour `colour` (of 3^dim) and cell-local node b.
 void asm_probe_set(const GeomDesc& g, int colour, int b, double val, double* x, hipStream_t s);

@@ -4,6 +4,10 @@
 // applied as d one-dimensional sweeps; the restriction R = P^T uses the transposed
 // 1D matrices.  Dirichlet rows and columns are already removed from the 1D factors.  Each sweep is a banded 1D contraction with unit-stride access
 // along x, so consecutive lanes read consecutive addresses in every direction.
+//
+// Temporal transfers (k- and tau-coarsening, Section 3.2) act on the temporal index only,
+// "I (x) P^tau": every interior node x maps its n_c coarse temporal values to n_f fine ones
+// with the dense (n_f x n_c) matrix P_t, or back with P_t^T; Dirichlet nodes carry zero.
 #include "kernels.hpp"
 
 namespace stmg {
@@ -37,7 +41,50 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __re
   else *dst = s;
 }
 
+// one thread per lattice node: load the node's input planes (coalesced over x), write every
+// output plane.  P (nf x nc, row-major) is staged in LDS.
+template <class T>
+__global__ __launch_bounds__(256) void k_time_transfer(const T* __restrict__ P, int nf, int nc, long long nx,
+                                                       const unsigned char* __restrict__ mask,
+                                                       const T* __restrict__ in, T* __restrict__ out, int mode) {
+  __shared__ T Ps[TT_MAX * TT_MAX];
+  for (int i = threadIdx.x; i < nf * nc; i += blockDim.x) Ps[i] = P[i];
+  __syncthreads();
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const bool inner = mask[x] != 0;
+  const int nin = mode == 2 ? nf : nc, nout = mode == 2 ? nc : nf;
+  T v[TT_MAX];
+  for (int j = 0; j < nin; ++j) v[j] = inner ? in[(long long)j * nx + x] : (T)0;
+  for (int i = 0; i < nout; ++i) {
+    T s = 0;
+    if (mode == 2)
+      for (int j = 0; j < nin; ++j) s += Ps[j * nc + i] * v[j];      // P^T
+    else
+      for (int j = 0; j < nin; ++j) s += Ps[i * nc + j] * v[j];      // P
+    T* dst = out + (long long)i * nx + x;
+    if (mode == 1) *dst += s;
+    else *dst = s;
+  }
+}
+
 }  // namespace
+
+template <class T>
+void time_transfer(const T* P, int nf, int nc, long long nx, const unsigned char* mask, const T* in, T* out,
+                   int mode, hipStream_t s) {
+  if (nf < 1 || nc < 1 || nf > TT_MAX || nc > TT_MAX) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the temporal transfer");
+  if (mode < 0 || mode > 2) fail(STMG_E_ARG, "temporal transfer mode");
+  if (nx <= 0) return;
+  hipLaunchKernelGGL(k_time_transfer<T>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, P, nf, nc, nx, mask,
+                     in, out, mode);
+  STMG_CHECK_LAUNCH();
+}
+
+template void time_transfer<double>(const double*, int, int, long long, const unsigned char*, const double*,
+                                    double*, int, hipStream_t);
+template void time_transfer<float>(const float*, int, int, long long, const unsigned char*, const float*, float*,
+                                   int, hipStream_t);
 
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
