@@ -34,7 +34,11 @@ def log(msg):
 
 FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP64_MFMA_PEAK_TFLOPS = 78.6
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "st_apply3_heat3d_q4_dg2_c8_hbm_traffic.md")
+# committed FETCH_SIZE / WRITE_SIZE summaries of the finest-level kernels at the default workload
+TRAFFIC_PROFILES = {
+    "operator": (os.path.join(ROOT, "profiles", "st_apply3_heat3d_q4_dg2_c8_hbm_traffic.md"), "op_apply.hip"),
+    "smoother": (os.path.join(ROOT, "profiles", "k_asm_mfma_heat3d_q4_dg2_c8_hbm_traffic.md"), "asm.hip"),
+}
 
 
 def code_hash(path):
@@ -46,22 +50,22 @@ def code_hash(path):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def operator_traffic(cfg):
-    """HBM bytes per finest-level operator apply from the committed FETCH_SIZE/WRITE_SIZE summary,
-    or None when the workload differs or the kernel source changed since it was measured."""
-    import hashlib
-    if cfg.name != "heat3d_32cube_Q4_perturbed_dG2_c8" or not os.path.exists(TRAFFIC_PROFILE):
+def kernel_traffic(cfg, key):
+    """HBM bytes per finest-level apply of kernel `key` ("operator" or "smoother") from its committed
+    FETCH_SIZE/WRITE_SIZE summary, or None when the workload differs or the kernel source changed
+    since it was measured."""
+    path, src = TRAFFIC_PROFILES[key]
+    if cfg.name != "heat3d_32cube_Q4_perturbed_dG2_c8" or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_PROFILE):
-        if ":" in line and line.split(":")[0].strip() in ("operator_traffic_bytes_per_apply",
-                                                          "operator_source_sha256_16"):
+    for line in open(path):
+        if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_apply", "source_sha256_16"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    cur = code_hash(os.path.join(ROOT, "paper_2408_04372_amd", "csrc", "op_apply.hip"))
-    if vals.get("operator_source_sha256_16") != cur:
+    cur = code_hash(os.path.join(ROOT, "paper_2408_04372_amd", "csrc", src))
+    if vals.get("source_sha256_16") != cur or "traffic_bytes_per_apply" not in vals:
         return None
-    return float(vals["operator_traffic_bytes_per_apply"])
+    return float(vals["traffic_bytes_per_apply"])
 
 
 def kernel_roofline(h, cfg, ks, dtype_bytes=8):
@@ -97,6 +101,7 @@ def kernel_roofline(h, cfg, ks, dtype_bytes=8):
                     "TFLOPs": fl / t / 1e12, "frac_hbm": nb / t / 1e9 / HBM_PEAK_GBS,
                     "frac_flops": fl / t / 1e12 / peak_f,
                     "bound": ("alu" if key == "operator" else "mfma") if t_fl > t_mem else "hbm",
+                    "peak_flops": peak_f, "traffic": kernel_traffic(cfg, key),
                     "speed_of_light_s": max(t_mem, t_fl)}
     return out
 
@@ -220,11 +225,11 @@ def main():
     if d["bound"] == "hbm":
         ach, peak, unit, frac = d["GBs"], HBM_PEAK_GBS, "GB/s", d["frac_hbm"]
     else:
-        ach, peak, unit, frac = d["TFLOPs"], FP64_VALU_PEAK_TFLOPS, "TFLOP/s", d["frac_flops"]
+        ach, peak, unit, frac = d["TFLOPs"], d["peak_flops"], "TFLOP/s", d["frac_flops"]
     roofline = {"kernel": "smoother (k_asm_mfma, finest level, 8 colour dispatches)" if dominant == "smoother"
                 else "operator (st_apply3, finest level, 8 colour dispatches)",
                 "bound": d["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": frac,
-                "traffic": operator_traffic(cfg) if dominant == "operator" else None,
+                "traffic": kernel_traffic(cfg, dominant),
                 "avg_launch_s": d["avg_s"], "bytes_per_launch": d["bytes"], "flops_per_launch": d["flops"],
                 "frac_hbm": d["frac_hbm"], "frac_flops": d["frac_flops"]}
     extras = {"kernels": kr, "kernel_counts": ks}
@@ -238,6 +243,22 @@ def main():
         h.set_precision(0)
         extras["time_to_solution_s"] = {"fp64": elapsed / args.steps, "fp32_vcycle": inf32["seconds"]}
         extras["iterations"] = {"fp64": iters / args.steps, "fp32_vcycle": inf32["iterations"]}
+        # temporal levels below the spatial ones (k to its minimum, then tau doubled)
+        t1 = time.time()
+        htm = Handle(cfg, verts, coef, vcycle_dtypes=1, precision=0, rtol=1e-8, restart=30, max_iter=300,
+                     omega=-1.5, time_mg=1)
+        tm_setup = time.time() - t1
+        x.zero_()
+        htm.solve(b, x)
+        x.zero_()
+        inftm = htm.solve(b, x)
+        extras["time_mg"] = {"levels": htm.info["n_levels"], "n_t_level": htm.info["n_t_level"],
+                             "coarse_unknowns": htm.info["coarse_unknowns"], "setup_s": tm_setup,
+                             "iterations": inftm["iterations"], "seconds": inftm["seconds"],
+                             "rel_residual": inftm["rel_residual"],
+                             "spatial_only": {"levels": h.info["n_levels"],
+                                              "coarse_unknowns": h.info["coarse_unknowns"]}}
+        htm.close()
         if not args.no_learned:
             # learned stage: a network trained on the GPU on plain-STMG pairs of an 8^3-cell box
             # with the same mesh width, degrees and time step, then used on the full problem
