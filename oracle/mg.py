@@ -298,7 +298,8 @@ class Hierarchy:
         # (space, slab) per level, coarsest first: with time_mg, temporal levels on the coarsest
         # spatial mesh come below the spatial ones ("first in space, then in time")
         pairs = [(sp, fine_op.slab) for sp in spaces]
-        if time_mg:
+        # no temporal levels when the coarsest spatial mesh has no interior node (nothing to coarsen)
+        if time_mg and all(n >= 3 for n in spaces[0].nodes):
             for sl in temporal.time_levels(fine_op.slab):
                 pairs.insert(0, (spaces[0], sl))
         self.n_smooth = n_smooth
