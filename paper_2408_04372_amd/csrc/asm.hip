@@ -214,7 +214,11 @@ __global__ __launch_bounds__(ABS) void k_asm_apply(GeomDesc g, ColourSet cs, int
 #pragma unroll
       for (int jj = 0; jj < JMAX; ++jj) {
         int j = jg + jj * JG;
-        if (j < n_t) cellbuf[(cell * n_t + j) * ns + o] = omega * acc[jj];
+        if (j < n_t) {
+          const int n = g.n;
+          const int lx = o % n, ly = (o / n) % n, lz = g.dim == 3 ? o / (n * n) : 0;
+          cellbuf[ebuf_index(g, j, cx, cy, cz, lx, ly, lz)] = omega * acc[jj];
+        }
       }
     } else if (in) {
 #pragma unroll
@@ -402,8 +406,11 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
   __syncthreads();
   if (cellbuf) {
     if (a < NS) {
+      const int lx = a % N, ly = (a / N) % N, lz = DIM == 3 ? a / (N * N) : 0;
+      const long long e0 = ebuf_index(g, 0, cx, cy, cz, lx, ly, lz);
+      const long long es = ebuf_index(g, 1, 0, 0, 0, 0, 0, 0);
 #pragma unroll 4
-      for (int j = j0; j < n_t; j += JSTEP) cellbuf[(cell * n_t + j) * NS + a] = omega * P[a * LD + j];
+      for (int j = j0; j < n_t; j += JSTEP) cellbuf[e0 + j * es] = omega * P[a * LD + j];
     }
   } else if (in) {
 #pragma unroll 4

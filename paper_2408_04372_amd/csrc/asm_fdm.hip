@@ -117,11 +117,11 @@ __global__ __launch_bounds__(256) void k_asm_fdm(GeomDesc g, ColourSet cs, int n
   // add omega Z to the interior nodes (or to this cell's slot of the buffer)
   for (int idx = tid; idx < n_t * NS; idx += blockDim.x) {
     const int j = idx / NS, a = idx % NS;
+    const int lx = a % N, ly = (a / N) % N, lz = DIM == 3 ? a / (N * N) : 0;
     if (cellbuf) {
-      cellbuf[(cell * n_t + j) * NS + a] = omega * X[idx];
+      cellbuf[ebuf_index(g, j, cc[0], cc[1], cc[2], lx, ly, lz)] = omega * X[idx];
       continue;
     }
-    const int lx = a % N, ly = (a / N) % N, lz = DIM == 3 ? a / (N * N) : 0;
     const int gx = cc[0] * p + lx, gy = cc[1] * p + ly, gz = cc[2] * p + lz;
     const bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 &&
                     (DIM == 2 || (gz != 0 && gz != g.nn[2] - 1));

@@ -169,45 +169,47 @@ __global__ void k_norm_part(const T* __restrict__ x, long long n, double* part) 
   if (threadIdx.x == 0) { part[blockIdx.x * PS] = s; part[blockIdx.x * PS + 1] = b; }
 }
 
+// grid: x = chunks of the (gx, gy) plane, y = gz, z = temporal plane; 32-bit index math
 template <class T>
-__global__ void k_cell_gather(GeomDesc g, int n_t, const T* __restrict__ cb, T* __restrict__ y) {
-  const int n = g.n, p = g.p;
-  const int nq = g.dim == 3 ? n * n * n : n * n;
-  const long long total = (long long)n_t * g.nx;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long j = idx / g.nx, node = idx - j * g.nx;
-    const int gx = (int)(node % g.nn[0]);
-    const int gy = (int)((node / g.nn[0]) % g.nn[1]);
-    const int gz = g.dim == 3 ? (int)(node / ((long long)g.nn[0] * g.nn[1])) : 0;
-    if (gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1) continue;
-    if (g.dim == 3 && (gz == 0 || gz == g.nn[2] - 1)) continue;
-    // cells containing the node along each axis (one, or two on a cell face)
-    const int x1 = gx / p, x0 = (gx % p == 0) ? x1 - 1 : x1;
-    const int y1 = gy / p, y0 = (gy % p == 0) ? y1 - 1 : y1;
-    const int z1 = g.dim == 3 ? gz / p : 0, z0 = (g.dim == 3 && gz % p == 0) ? z1 - 1 : z1;
-    T sum = 0;
-    for (int cz = z0; cz <= z1; ++cz)
-      for (int cy = y0; cy <= y1; ++cy)
-        for (int cx = x0; cx <= x1; ++cx) {
-          const long long cell = ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
-          const int l = ((gz - cz * p) * n + (gy - cy * p)) * n + (gx - cx * p);
-          sum += cb[(cell * n_t + j) * nq + l];
-        }
-    y[idx] += sum;
+__global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __restrict__ cb, T* y, const T* base,
+                                                     int overwrite) {
+  const int p = g.p;
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= g.nn[0] * g.nn[1]) return;
+  const int gx = local % g.nn[0], gy = local / g.nn[0], gz = blockIdx.y, j = blockIdx.z;
+  const long long idx = ((long long)j * g.nn[2] + gz) * g.nn[1] * g.nn[0] + local;
+  if (gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1 ||
+      (g.dim == 3 && (gz == 0 || gz == g.nn[2] - 1))) {
+    if (overwrite) y[idx] = base ? base[idx] : (T)0;
+    return;
   }
+  // cells containing the node along each axis (one, or two on a cell face)
+  const int x1 = gx / p, x0 = (gx % p == 0) ? x1 - 1 : x1;
+  const int y1 = gy / p, y0 = (gy % p == 0) ? y1 - 1 : y1;
+  const int z1 = g.dim == 3 ? gz / p : 0, z0 = (g.dim == 3 && gz % p == 0) ? z1 - 1 : z1;
+  T sum = 0;
+  for (int cz = z0; cz <= z1; ++cz)
+    for (int cy = y0; cy <= y1; ++cy)
+      for (int cx = x0; cx <= x1; ++cx)
+        sum += cb[ebuf_index(g, j, cx, cy, cz, gx - cx * p, gy - cy * p, gz - cz * p)];
+  if (overwrite) y[idx] = (base ? base[idx] : (T)0) + sum;
+  else y[idx] += sum;
 }
 
 }  // namespace
 
-template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s) {
-  long long n = (long long)n_t * g.nx;
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_cell_gather<T>, dim3(grid_for(n)), dim3(BS), 0, s, g, n_t, cb, y);
+template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s, const T* base,
+                                    bool overwrite) {
+  const long long plane = (long long)g.nn[0] * g.nn[1];
+  const int nz = g.dim == 3 ? g.nn[2] : 1;
+  if (plane * nz * n_t <= 0) return;
+  if (plane > (1LL << 30) || nz > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the gather kernel");
+  dim3 grid((unsigned)((plane + 255) / 256), (unsigned)nz, (unsigned)n_t);
+  hipLaunchKernelGGL(k_cell_gather<T>, grid, dim3(256), 0, s, g, cb, y, base, overwrite ? 1 : 0);
   STMG_CHECK_LAUNCH();
 }
-template void cell_gather<double>(const GeomDesc&, int, const double*, double*, hipStream_t);
-template void cell_gather<float>(const GeomDesc&, int, const float*, float*, hipStream_t);
+template void cell_gather<double>(const GeomDesc&, int, const double*, double*, hipStream_t, const double*, bool);
+template void cell_gather<float>(const GeomDesc&, int, const float*, float*, hipStream_t, const float*, bool);
 
 template <class T> void fill(T* y, T v, long long n, hipStream_t s) {
   if (n <= 0) return;

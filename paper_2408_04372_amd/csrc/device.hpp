@@ -27,6 +27,7 @@ struct GeomDesc {
 template <class T>
 struct TemporalDev {
   int n_t = 0;
+  int mnnz = 0, nnnz = 0;   // stored entries of M_T and N_T
   const int* mptr = nullptr; const int* mcol = nullptr; const T* mval = nullptr;
   const int* nptr = nullptr; const int* ncol = nullptr; const T* nval = nullptr;
 };
@@ -93,5 +94,17 @@ __device__ inline long long colour_cell(const ColourSet& cs, const GeomDesc& g, 
   return ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
 }
 inline int n_colours(int dim) { return dim == 3 ? 8 : 4; }
+
+// Per-cell buffer ("broken lattice"): every cell keeps its own copy of its n^d local nodes, laid
+// out as a lattice of nc * n points per direction (cell c, local node l at c * n + l), temporal
+// plane slowest.  Neighbouring cells write neighbouring runs, and a node-parallel gather reads
+// consecutive positions for consecutive nodes.
+__device__ inline long long ebuf_index(const GeomDesc& g, int j, int cx, int cy, int cz, int lx, int ly, int lz) {
+  const int n = g.n;
+  const long long ex = (long long)g.nc[0] * n, ey = (long long)g.nc[1] * n;
+  const long long ez = g.dim == 3 ? (long long)g.nc[2] * n : 1;
+  const long long zz = g.dim == 3 ? (long long)cz * n + lz : 0;
+  return (((long long)j * ez + zz) * ey + (long long)cy * n + ly) * ex + (long long)cx * n + lx;
+}
 
 }  // namespace stmg

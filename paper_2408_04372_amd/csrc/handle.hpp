@@ -118,6 +118,7 @@ struct stmg_handle {
   stmg::CnnState* cnn = nullptr;
   stmg::DevBuf vel;            // wave velocity recovery: M_T^{-1} A_T and the u0 / v0 weights
   stmg::DevBuf rhsc, rhs3x, rhs3y, rhs_mp, rhs_mc, rhs_mv, rhs_np, rhs_nc, rhs_nv;   // slab right-hand sides
+  int rhs_mnnz = 0, rhs_nnnz = 0;
   ~stmg_handle();
 };
 
@@ -136,7 +137,7 @@ void slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u
 void node_coordinates(stmg_handle* h, double* xyz);
 void point_values(stmg_handle* h, const double* U, int n_planes, int npts, const double* pts, double* out);
 // CSR of the nonzeros of a dense matrix (hierarchy.hip)
-template <class T> void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s);
+template <class T> int upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s);
 // learned stage (cnn.hip)
 void cnn_create(stmg_handle* h, int n_layers, const int* channels);
 long long cnn_param_count(stmg_handle* h);

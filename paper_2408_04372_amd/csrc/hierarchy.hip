@@ -107,9 +107,9 @@ namespace {
 
 }  // namespace
 
-// CSR of the nonzeros of a dense n x n matrix
+// CSR of the nonzeros of a dense n x n matrix; returns the number of nonzeros
 template <class T>
-void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s) {
+int upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s) {
   std::vector<int> p{0}, c;
   std::vector<T> v;
   for (int i = 0; i < A.r; ++i) {
@@ -117,21 +117,23 @@ void upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStre
       if (A(i, j) != 0.0) { c.push_back(j); v.push_back((T)A(i, j)); }
     p.push_back((int)c.size());
   }
+  const int nnz = (int)c.size();
   if (c.empty()) { c.push_back(0); v.push_back(0); }
   ptr = upload(p, s);
   col = upload(c, s);
   val = upload(v, s);
+  return nnz;
 }
 
-template void upload_csr<double>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
-template void upload_csr<float>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
+template int upload_csr<double>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
+template int upload_csr<float>(const hm::Mat&, DevBuf&, DevBuf&, DevBuf&, hipStream_t);
 
 namespace {
 
 template <class T>
 void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {
-  upload_csr<T>(tm.M_T, tb.mptr, tb.mcol, tb.mval, s);
-  upload_csr<T>(tm.N_T, tb.nptr, tb.ncol, tb.nval, s);
+  tb.dev.mnnz = upload_csr<T>(tm.M_T, tb.mptr, tb.mcol, tb.mval, s);
+  tb.dev.nnnz = upload_csr<T>(tm.N_T, tb.nptr, tb.ncol, tb.nval, s);
   tb.dev.n_t = tm.n_t;
   tb.dev.mptr = tb.mptr.template as<int>(); tb.dev.mcol = tb.mcol.template as<int>(); tb.dev.mval = tb.mval.template as<T>();
   tb.dev.nptr = tb.nptr.template as<int>(); tb.dev.ncol = tb.ncol.template as<int>(); tb.dev.nval = tb.nval.template as<T>();
@@ -323,9 +325,9 @@ void setup_smoother(stmg_handle* h, Level& L) {
   Mp(0, 0) = 1.0;
   Np(1, 1) = 1.0;
   DevBuf mp, mc, mv, np_, nc, nv;
-  upload_csr<double>(Mp, mp, mc, mv, s);
-  upload_csr<double>(Np, np_, nc, nv, s);
   TemporalDev<double> tp2;
+  tp2.mnnz = upload_csr<double>(Mp, mp, mc, mv, s);
+  tp2.nnnz = upload_csr<double>(Np, np_, nc, nv, s);
   tp2.n_t = 2;
   tp2.mptr = mp.as<int>(); tp2.mcol = mc.as<int>(); tp2.mval = mv.as<double>();
   tp2.nptr = np_.as<int>(); tp2.ncol = nc.as<int>(); tp2.nval = nv.as<double>();
@@ -386,7 +388,7 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
   d.u.alloc(n);
   d.r.alloc(n);
   d.f.alloc(n);
-  if (L.g.ncells <= TWO_PHASE_MAX_CELLS) {
+  if (two_phase<T>(L.g.ncells)) {
     const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
     d.cellbuf.alloc(sizeof(T) * L.g.ncells * n_t * nq);
   }
@@ -486,6 +488,11 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     cur.ratio *= 2;
     shapes.push_back(cur);
   }
+  // temporal levels on the coarsest spatial mesh, if it has an interior node at all
+  bool has_interior = true;
+  for (int d = 0; d < dim; ++d)
+    if ((long long)cur.cells[d] * cur.p + 1 < 3) has_interior = false;
+  if (!has_interior) h->tsets.resize(1);
   for (size_t t = 1; t < h->tsets.size(); ++t) {
     cur.t = (int)t;
     shapes.push_back(cur);
@@ -567,6 +574,11 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     bool coarsest = (l + 1 == h->levels.size());
     if (L.has64) alloc_work<double>(L, L.n_t(), coarsest);
     if (L.has32) alloc_work<float>(L, L.n_t(), coarsest);
+    // the outer FP64 operator of the solver runs on the finest level in every mode
+    if (l == 0 && !L.has64 && two_phase<double>(L.g.ncells)) {
+      const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
+      L.d64.cellbuf.alloc(sizeof(double) * L.g.ncells * L.n_t() * nq);
+    }
     if (!coarsest) setup_smoother(h, L);
     else setup_coarse(h, L);
   }
@@ -586,9 +598,10 @@ template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
   Level& L = *h->levels[level];
   hipStream_t s = h->stream;
   long long n = L.nst(L.n_t());
-  fill<T>(y, (T)0, n, s);
+  T* cb = ldata<T>(L).cellbuf.template as<T>();
+  if (!cb) fill<T>(y, (T)0, n, s);      // the per-cell buffer path writes y itself
   if (level == 0) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(L), x, y, (T)1, s, ldata<T>(L).cellbuf.template as<T>());
+  st_apply<T>(L.g, L.lt, tdev<T>(L), x, y, (T)1, s, cb, nullptr, cb != nullptr);
   if (level == 0) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)1, x, (T)0, y, s);
 }
@@ -597,10 +610,11 @@ template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
 template <class T> static void residual(stmg_handle* h, Level& L, const T* f, const T* u, T* r) {
   hipStream_t s = h->stream;
   long long n = L.nst(L.n_t());
-  copy<T>(f, r, n, s);
+  T* cb = ldata<T>(L).cellbuf.template as<T>();
+  if (!cb) copy<T>(f, r, n, s);         // the per-cell buffer path reads f in its gather
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(L), u, r, (T)-1, s, ldata<T>(L).cellbuf.template as<T>());
+  st_apply<T>(L.g, L.lt, tdev<T>(L), u, r, (T)-1, s, cb, f, cb != nullptr);
   if (fine) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)-1, u, (T)1, r, s);
 }

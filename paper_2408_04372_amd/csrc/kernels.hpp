@@ -23,12 +23,19 @@ LevelTables make_level_tables(int p);
 // per colour); without it the cells are processed colour by colour.
 template <class T>
 void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
-              T scale, hipStream_t s, T* cellbuf = nullptr);
-// Levels with at most this many cells use the per-cell buffer path.
+              T scale, hipStream_t s, T* cellbuf = nullptr, const T* base = nullptr, bool overwrite = false);
+// Levels with at most this many cells use the per-cell buffer path in every precision; in FP64
+// every level does (there the single launch over all cells plus a gather beats 2^d colour
+// launches with read-modify-write, in FP32 the colour path is faster on large levels).
 constexpr long long TWO_PHASE_MAX_CELLS = 4096;
-// y[j][g] += sum over the cells K containing interior node g of cb[K][j][local index of g]
-// (fixed cell order); Dirichlet nodes untouched.
-template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s);
+template <class T> inline bool two_phase(long long ncells) {
+  return ncells <= TWO_PHASE_MAX_CELLS || sizeof(T) == sizeof(double);
+}
+// Gather of the per-cell buffer (fixed cell order) into the lattice vector.
+// y += sum of the cell contributions (overwrite = false), or y = base + sum (overwrite = true,
+// base may be null for zero; Dirichlet nodes then receive base, or zero)
+template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s,
+                                    const T* base = nullptr, bool overwrite = false);
 
 // ---- vector kernels (blas.hip) --------------------------------------------------------------
 template <class T> void fill(T* y, T v, long long n, hipStream_t s);

@@ -32,7 +32,7 @@ struct OpArgs {
   TemporalDev<T> tp;
   const T* x;
   T* y;
-  T* cellbuf;     // non-null: write each cell's contribution to cellbuf[cell][n_t][NQ]
+  T* cellbuf;     // non-null: write each cell's contribution to its slot of the per-cell buffer
   T scale;
   int cpw;        // cells per workgroup
   int nblocks;
@@ -210,7 +210,9 @@ __device__ inline void xz_to_xy(T* scr, int t, const T (&in)[N][N], T (&out)[N][
   __syncthreads();
 }
 
-template <class T, int N>
+// CB: write each cell's contribution to the per-cell buffer instead of adding it to y (a separate
+// instantiation, so the colour path carries no code of the buffer path)
+template <class T, int N, bool CB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void st_apply3(OpArgs<T, N> A,
                                                                                        ColourSet cs) {
   constexpr int NQ = N * N * N;
@@ -220,6 +222,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const int cpw = A.cpw;
   T* geo = reinterpret_cast<T*>(smem_raw);                  // [cpw][NQ][GS]
   T* xs = geo + (size_t)cpw * NQ * GS;                      // [cpw][n_t][NQ] + dummy panel: input, scratch, output
+  // temporal CSR of M_T and N_T, copied to LDS so the mixing loops read no global memory
+  const int mnnz = A.tp.mnnz, nnnz = A.tp.nnnz;
+  T* mval_s = xs + (size_t)(cpw * n_t + 1) * NQ;
+  T* nval_s = mval_s + mnnz;
+  int* mptr_s = reinterpret_cast<int*>(nval_s + nnnz);
+  int* nptr_s = mptr_s + n_t + 1;
+  int* mcol_s = nptr_s + n_t + 1;
+  int* ncol_s = mcol_s + mnnz;
   const GeomDesc& g = A.g;
   const int p = N - 1;
   const int tid = threadIdx.x;
@@ -231,26 +241,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const long long li0 = (long long)xcd_swizzle(blockIdx.x, A.nblocks) * cpw;
   const int ncell = (int)((cs.count - li0) < cpw ? (cs.count - li0) : cpw);
 
-  // geometry factors of this block's cells
-  for (int idx = tid; idx < ncell * NQ; idx += nthr) {
-    int lc = idx / NQ, q = idx - lc * NQ;
+  for (int e = threadIdx.x; e < mnnz; e += blockDim.x) { mval_s[e] = A.tp.mval[e]; mcol_s[e] = A.tp.mcol[e]; }
+  for (int e = threadIdx.x; e < nnnz; e += blockDim.x) { nval_s[e] = A.tp.nval[e]; ncol_s[e] = A.tp.ncol[e]; }
+  for (int e = threadIdx.x; e <= n_t; e += blockDim.x) { mptr_s[e] = A.tp.mptr[e]; nptr_s[e] = A.tp.nptr[e]; }
+  // geometry factors of this block's cells (the cell loop is uniform, so cell indices and vertex
+  // addresses stay scalar)
+  for (int lc = 0; lc < ncell; ++lc) {
     int cx, cy, cz;
-    long long cell = colour_cell(cs, g, li0 + lc, cx, cy, cz);
-    int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
-    double o[7];
-    geometry<3, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, cz, qx, qy, qz, q, o);
-    T* dst = geo + ((size_t)lc * NQ + q) * GS;
+    const long long cell = colour_cell(cs, g, li0 + lc, cx, cy, cz);
+    for (int q = tid; q < NQ; q += nthr) {
+      const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+      double o[7];
+      geometry<3, N>(g, A.tab.gq, A.tab.gw, cell, cx, cy, cz, qx, qy, qz, q, o);
+      T* dst = geo + ((size_t)lc * NQ + q) * GS;
 #pragma unroll
-    for (int s2 = 0; s2 < GS; ++s2) dst[s2] = (T)o[s2];
+      for (int s2 = 0; s2 < GS; ++s2) dst[s2] = (T)o[s2];
+    }
   }
-  // stage every temporal plane of the cells (Dirichlet nodes read as zero), node index fastest
-  // (batches of UB loads are issued before their LDS stores, so the latencies overlap)
+  // stage every temporal plane of the cells (Dirichlet nodes read as zero), node index fastest;
+  // batches of UB loads are issued before their LDS stores, so the latencies overlap.  With at
+  // least NQ threads each thread keeps one local node (offset and Dirichlet flag computed once per
+  // cell) and walks the planes j0, j0 + npl, ...; otherwise the (plane, node) pairs are split flat.
   constexpr int UB = 24;
   const int total = n_t * NQ;
+  const int npl = nthr >= NQ ? nthr / NQ : 0;
+  const int my_node = npl ? tid % NQ : 0, my_j0 = npl ? tid / NQ : 0;
+  const int mlx = my_node % N, mly = (my_node / N) % N, mlz = my_node / (N * N);
   for (int lc = 0; lc < ncell; ++lc) {
     int cx, cy, cz;
     colour_cell(cs, g, li0 + lc, cx, cy, cz);
     T* dst = xs + (size_t)lc * n_t * NQ;
+    if (npl) {
+      if (my_j0 >= npl) continue;
+      const int gx = cx * p + mlx, gy = cy * p + mly, gz = cz * p + mlz;
+      const bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 &&
+                      gz != g.nn[2] - 1;
+      const T* src = A.x + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
+      int jb = my_j0;
+      for (; jb + (UB - 1) * npl < n_t; jb += UB * npl) {    // full batches: no per-load guard
+        T v[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) v[u] = in ? src[(long long)(jb + u * npl) * plane] : (T)0;
+#pragma unroll
+        for (int u = 0; u < UB; ++u) dst[(jb + u * npl) * NQ + my_node] = v[u];
+      }
+      for (; jb < n_t; jb += npl) dst[jb * NQ + my_node] = in ? src[(long long)jb * plane] : (T)0;
+      continue;
+    }
     for (int base = tid; base < total; base += UB * nthr) {
       T v[UB];
 #pragma unroll
@@ -284,17 +321,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     for (int x = 0; x < N; ++x) { a[y][x] = 0; b[y][x] = 0; }
   if (act) {
     const T* xc = xs + (size_t)lc * n_t * NQ + t * N * N;
-    for (int k = A.tp.mptr[i]; k < A.tp.mptr[i + 1]; ++k) {
-      const T c = A.tp.mval[k];
-      const T* xj = xc + (size_t)A.tp.mcol[k] * NQ;
+    for (int k = mptr_s[i]; k < mptr_s[i + 1]; ++k) {
+      const T c = mval_s[k];
+      const T* xj = xc + (size_t)mcol_s[k] * NQ;
 #pragma unroll
       for (int y = 0; y < N; ++y)
 #pragma unroll
         for (int x = 0; x < N; ++x) a[y][x] += c * xj[y * N + x];
     }
-    for (int k = A.tp.nptr[i]; k < A.tp.nptr[i + 1]; ++k) {
-      const T c = A.tp.nval[k];
-      const T* xj = xc + (size_t)A.tp.ncol[k] * NQ;
+    for (int k = nptr_s[i]; k < nptr_s[i + 1]; ++k) {
+      const T c = nval_s[k];
+      const T* xj = xc + (size_t)ncol_s[k] * NQ;
 #pragma unroll
       for (int y = 0; y < N; ++y)
 #pragma unroll
@@ -375,13 +412,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
       for (int x = 0; x < N; ++x) scr[(t * N + y) * N + x] = t2[y][x];
   }
   __syncthreads();
-  if (A.cellbuf) {
+  if constexpr (CB) {
+    const long long es = ebuf_index(g, 1, 0, 0, 0, 0, 0, 0);     // plane stride of the buffer
     for (int lc2 = 0; lc2 < ncell; ++lc2) {
       int cx, cy, cz;
-      const long long cell = colour_cell(cs, g, li0 + lc2, cx, cy, cz);
+      colour_cell(cs, g, li0 + lc2, cx, cy, cz);
       const T* src = xs + (size_t)lc2 * n_t * NQ;
-      T* dst = A.cellbuf + cell * n_t * NQ;
-      for (int idx = tid; idx < n_t * NQ; idx += nthr) dst[idx] = A.scale * src[idx];
+      if (npl) {
+        if (my_j0 >= npl) continue;
+        T* dst = A.cellbuf + ebuf_index(g, 0, cx, cy, cz, mlx, mly, mlz);
+        for (int j = my_j0; j < n_t; j += npl) dst[j * es] = A.scale * src[j * NQ + my_node];
+        continue;
+      }
+      for (int idx = tid; idx < n_t * NQ; idx += nthr) {
+        const int j = idx / NQ, node = idx - j * NQ;
+        const int lx = node % N, ly = (node / N) % N, lz = node / (N * N);
+        A.cellbuf[ebuf_index(g, j, cx, cy, cz, lx, ly, lz)] = A.scale * src[idx];
+      }
+    }
+    return;
+  }
+  if (npl) {
+    // one local node per thread, as in the staging
+    if (my_j0 >= npl) return;
+    for (int lc2 = 0; lc2 < ncell; ++lc2) {
+      int cx, cy, cz;
+      colour_cell(cs, g, li0 + lc2, cx, cy, cz);
+      const int gx = cx * p + mlx, gy = cy * p + mly, gz = cz * p + mlz;
+      const bool in = gx != 0 && gx != g.nn[0] - 1 && gy != 0 && gy != g.nn[1] - 1 && gz != 0 &&
+                      gz != g.nn[2] - 1;
+      if (!in) continue;
+      T* dst = A.y + ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
+      const T* src = xs + (size_t)lc2 * n_t * NQ + my_node;
+      int jb = my_j0;
+      for (; jb + (UB - 1) * npl < n_t; jb += UB * npl) {    // full batches: no per-load guard
+        T v[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) v[u] = dst[(long long)(jb + u * npl) * plane];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) dst[(long long)(jb + u * npl) * plane] = v[u] + A.scale * src[(jb + u * npl) * NQ];
+      }
+      for (; jb < n_t; jb += npl) dst[(long long)jb * plane] += A.scale * src[jb * NQ];
     }
     return;
   }
@@ -512,12 +583,10 @@ __global__ __launch_bounds__(64) void st_apply2(OpArgs<T, N> A, ColourSet cs) {
     rows_t<T, N>(S, bh, t0);    // [y][qx]
     cols_t<T, N>(S, t0, ah);    // [y][x]
     if (A.cellbuf) {
-      const long long cell = (long long)cy * g.nc[0] + cx;
-      T* cb = A.cellbuf + (cell * n_t + i) * NQ;
 #pragma unroll
       for (int y = 0; y < N; ++y)
 #pragma unroll
-        for (int x = 0; x < N; ++x) cb[y * N + x] = A.scale * ah[y][x];
+        for (int x = 0; x < N; ++x) A.cellbuf[ebuf_index(g, i, cx, cy, 0, x, y, 0)] = A.scale * ah[y][x];
       continue;
     }
     T* yi = A.y + (long long)i * plane + base;
@@ -559,7 +628,7 @@ int pick_cpw(int teams, int n_t) {
 
 template <class T, int N>
 void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp,
-                  const T* x, T* y, T scale, hipStream_t s, T* cellbuf) {
+                  const T* x, T* y, T scale, hipStream_t s, T* cellbuf, const T* base, bool overwrite) {
   OpArgs<T, N> A;
   A.tab = make_tables<T, N>(lt);
   A.g = g;
@@ -575,19 +644,20 @@ void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>
     // all n_t outputs of cpw cells in one round: cpw * n_t teams of N lanes, at most 256 lanes
     int per_cell = N * tp.n_t;
     if (per_cell > 256) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the operator kernel");
+    const size_t csr = sizeof(T) * (size_t)(tp.mnnz + tp.nnnz) + sizeof(int) * (size_t)(2 * (tp.n_t + 1) + tp.mnnz + tp.nnnz);
     int best = 1;
     double be = -1.0;
     for (int c = 1; c * per_cell <= 256; ++c) {
       int lanes = c * per_cell;
       int th = (lanes + 63) / 64 * 64;
       double eff = (double)lanes / th;
-      size_t l = sizeof(T) * ((size_t)c * NQ * (7 + tp.n_t) + NQ);
+      size_t l = sizeof(T) * ((size_t)c * NQ * (7 + tp.n_t) + NQ) + csr;
       if (l > 64 * 1024) break;
       if (eff > be + 1e-9) { be = eff; best = c; }
     }
     A.cpw = best;
     threads = (A.cpw * per_cell + 63) / 64 * 64;
-    lds = sizeof(T) * ((size_t)A.cpw * NQ * (7 + tp.n_t) + NQ);
+    lds = sizeof(T) * ((size_t)A.cpw * NQ * (7 + tp.n_t) + NQ) + csr;
   } else {
     constexpr int NQ = N * N;
     A.cpw = pick_cpw(64, tp.n_t);
@@ -598,31 +668,35 @@ void launch_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>
     ColourSet cs = cellbuf ? all_cells(g) : colour_set(g, colour);
     if (cs.count == 0) continue;
     A.nblocks = ceil_div(cs.count, A.cpw);
-    if (g.dim == 3) hipLaunchKernelGGL((st_apply3<T, N>), dim3(A.nblocks), dim3(threads), lds, s, A, cs);
+    if (g.dim == 3) {
+      if (cellbuf) hipLaunchKernelGGL((st_apply3<T, N, true>), dim3(A.nblocks), dim3(threads), lds, s, A, cs);
+      else hipLaunchKernelGGL((st_apply3<T, N, false>), dim3(A.nblocks), dim3(threads), lds, s, A, cs);
+    }
     else hipLaunchKernelGGL((st_apply2<T, N>), dim3(A.nblocks), dim3(64), lds, s, A, cs);
     STMG_CHECK_LAUNCH();
   }
-  if (cellbuf) cell_gather<T>(g, tp.n_t, cellbuf, y, s);
+  if (cellbuf) cell_gather<T>(g, tp.n_t, cellbuf, y, s, base, overwrite);
 }
 
 }  // namespace
 
 template <class T>
 void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
-              T scale, hipStream_t s, T* cellbuf) {
+              T scale, hipStream_t s, T* cellbuf, const T* base, bool overwrite) {
+  if (overwrite && !cellbuf) fail(STMG_E_UNSUPPORTED, "overwrite needs the per-cell buffer");
   if (g.ncells == 0 || tp.n_t == 0) return;
   switch (g.n) {
-    case 2: launch_apply<T, 2>(g, lt, tp, x, y, scale, s, cellbuf); break;
-    case 3: launch_apply<T, 3>(g, lt, tp, x, y, scale, s, cellbuf); break;
-    case 4: launch_apply<T, 4>(g, lt, tp, x, y, scale, s, cellbuf); break;
-    case 5: launch_apply<T, 5>(g, lt, tp, x, y, scale, s, cellbuf); break;
+    case 2: launch_apply<T, 2>(g, lt, tp, x, y, scale, s, cellbuf, base, overwrite); break;
+    case 3: launch_apply<T, 3>(g, lt, tp, x, y, scale, s, cellbuf, base, overwrite); break;
+    case 4: launch_apply<T, 4>(g, lt, tp, x, y, scale, s, cellbuf, base, overwrite); break;
+    case 5: launch_apply<T, 5>(g, lt, tp, x, y, scale, s, cellbuf, base, overwrite); break;
     default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
   }
 }
 
 template void st_apply<double>(const GeomDesc&, const LevelTables&, const TemporalDev<double>&,
-                               const double*, double*, double, hipStream_t, double*);
+                               const double*, double*, double, hipStream_t, double*, const double*, bool);
 template void st_apply<float>(const GeomDesc&, const LevelTables&, const TemporalDev<float>&,
-                              const float*, float*, float, hipStream_t, float*);
+                              const float*, float*, float, hipStream_t, float*, const float*, bool);
 
 }  // namespace stmg

@@ -130,13 +130,15 @@ void slab_rhs(stmg_handle* h, const double* F, const double* F0, const double* u
     Mp(0, 0) = 1.0;
     Np(1, 1) = 1.0;
     Np(2, 2) = 1.0;
-    upload_csr<double>(Mp, h->rhs_mp, h->rhs_mc, h->rhs_mv, s);
-    upload_csr<double>(Np, h->rhs_np, h->rhs_nc, h->rhs_nv, s);
+    h->rhs_mnnz = upload_csr<double>(Mp, h->rhs_mp, h->rhs_mc, h->rhs_mv, s);
+    h->rhs_nnnz = upload_csr<double>(Np, h->rhs_np, h->rhs_nc, h->rhs_nv, s);
     h->rhs3x.alloc(sizeof(double) * 3 * nx);
     h->rhs3y.alloc(sizeof(double) * 3 * nx);
   }
   TemporalDev<double> tp3;
   tp3.n_t = 3;
+  tp3.mnnz = h->rhs_mnnz;
+  tp3.nnnz = h->rhs_nnnz;
   tp3.mptr = h->rhs_mp.as<int>(); tp3.mcol = h->rhs_mc.as<int>(); tp3.mval = h->rhs_mv.as<double>();
   tp3.nptr = h->rhs_np.as<int>(); tp3.ncol = h->rhs_nc.as<int>(); tp3.nval = h->rhs_nv.as<double>();
   double* x3 = h->rhs3x.as<double>();

@@ -1,0 +1,136 @@
+"""Edge cases through the C ABI: a single spatial cell (one interior node, a coarsest level without
+unknowns), the largest temporal size the kernels take (n_t = 32), and error paths that need a
+created handle."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import stmg_inputs as si
+from oracle import mg, spacetime
+from tests.gpu_common import rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+SINGLE = si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=2, n_cells=(1, 1, 1), tau=0.1,
+                   coef="lognormal", coef_sigma=0.5, seed=71)
+NT32 = si.Config(dim=2, problem=1, time_method=0, p=2, k=3, n_time_cells=8, n_cells=(4, 4, 1), tau=0.05,
+                 coef="lognormal", coef_sigma=0.5, seed=72)
+NT32_3D = si.Config(dim=3, problem=0, time_method=1, p=2, k=4, n_time_cells=8, n_cells=(2, 2, 2), tau=0.05,
+                    perturb=0.1, seed=73)
+
+
+def _handle(cfg, verts, coef, **kw):
+    from paper_2408_04372_amd import Handle
+    kw.setdefault("vcycle_dtypes", 3)
+    return Handle(cfg, verts, coef, **kw)
+
+
+def _t(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype).view(-1)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg", [SINGLE, NT32, NT32_3D], ids=["single_cell", "nt32_2d", "nt32_3d_cgp"])
+@pytest.mark.parametrize("time_mg", [0, 1])
+def test_vcycle_and_solve(cfg, time_mg):
+    print(f"case {cfg.dim}d p{cfg.p} k{cfg.k} c{cfg.n_time_cells} n_t {cfg.n_t} time_mg {time_mg}", flush=True)
+    verts, coef = si.draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    H = mg.Hierarchy(op, omega_rule=-1.0, time_mg=bool(time_mg))
+    rng = np.random.default_rng(81)
+    x = rng.standard_normal(op.matrix().shape[0])
+    r = rng.standard_normal(op.matrix().shape[0])
+    ref = H.vcycle(r)
+    b = si.random_slab_vector(cfg, 82)
+    xd = op.solve(b)
+    h = _handle(cfg, verts, coef, omega=-1.0, time_mg=time_mg, rtol=1e-12, precision=0, max_iter=300)
+    try:
+        L = h.info["n_levels"]
+        assert L == len(H.levels)
+        assert h.info["n_t_level"] == [H.levels[L - 1 - l].op.n_t for l in range(L)]
+        for l in range(L - 1):
+            h.set_omega(l, H.levels[L - 1 - l].omega)
+        for dt, tol_op, tol_v in ((torch.float64, 1e-12, 1e-10), (torch.float32, 2e-5, 1e-4)):
+            y = torch.empty(x.size, dtype=dt, device=DEV)
+            h.vmult(_t(x, dt), y)
+            assert rel_err(_np(y), op.matrix() @ x) < tol_op, dt
+            z = torch.empty(r.size, dtype=dt, device=DEV)
+            h.vcycle(_t(r, dt), z)
+            assert rel_err(_np(z), ref) < tol_v, dt
+        u = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        info = h.solve(_t(b), u)
+        err = np.linalg.norm(_np(u) - xd.ravel()) / np.linalg.norm(xd)
+    finally:
+        h.close()
+    print(info, "error", err)
+    assert info["rel_residual"] <= 1e-12
+    assert err < 1e-10
+
+
+def test_time_mg_rejects_too_many_temporal_dofs():
+    from paper_2408_04372_amd import StmgError
+    cfg = si.Config(dim=2, problem=0, time_method=0, p=1, k=2, n_time_cells=12, n_cells=(2, 2, 1), tau=0.1)
+    verts, coef = si.draw_problem(cfg)
+    with pytest.raises(StmgError) as e:
+        _handle(cfg, verts, coef, time_mg=1)
+    assert e.value.code == 6
+
+
+def test_level_arguments_rejected():
+    cfg = si.paper_config(1)
+    verts, coef = si.draw_problem(cfg)
+    h = _handle(cfg, verts, coef)
+    try:
+        L = h.info["n_levels"]
+        buf = torch.zeros(h.size(0), dtype=torch.float64, device=DEV)
+        out = torch.zeros_like(buf)
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        assert h.lib.stmg_vmult(h.h, L, 0, p(buf), p(out)) == 1
+        assert h.lib.stmg_vmult(h.h, -1, 0, p(buf), p(out)) == 1
+        assert h.lib.stmg_vmult(h.h, 0, 0, p(buf), p(buf)) == 1          # aliasing
+        assert h.lib.stmg_vmult(h.h, 0, 2, p(buf), p(out)) == 1          # dtype
+        assert h.lib.stmg_smooth(h.h, L - 1, 0, p(buf), p(out), 1) == 1  # coarsest level
+        assert h.lib.stmg_prolongate(h.h, L - 1, 0, p(buf), p(out)) == 1
+        assert h.lib.stmg_restrict(h.h, L - 1, 0, p(buf), p(out)) == 1
+        assert len(h.lib.stmg_last_error()) > 0
+        # the handle stays usable after rejected calls
+        h.vmult(buf, out)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("name", ["heat3d_q2_dg1_pert", "wave3d_q3_cgp2_c4"])
+def test_bitwise_reproducible(name):
+    # no atomics on the operator, smoother, gather and reduction paths: two handles built from the
+    # same input give bitwise identical operator, smoother and V-cycle results
+    from tests.gpu_common import problem
+    cfg, verts, coef = problem(name)
+    outs = []
+    for _ in range(2):
+        h = _handle(cfg, verts, coef, omega=-1.0)
+        try:
+            g = torch.Generator(device=DEV)
+            g.manual_seed(9)
+            x = torch.randn(h.size(0), dtype=torch.float64, device=DEV, generator=g)
+            y, z, v = torch.empty_like(x), torch.zeros_like(x), torch.empty_like(x)
+            h.vmult(x, y)
+            h.smooth(x, z, steps=2)
+            h.vcycle(x, v)
+            torch.cuda.synchronize()
+            outs.append((list(h.info["omega"]), y.cpu(), z.cpu(), v.cpu()))
+        finally:
+            h.close()
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        assert torch.equal(a, b)
