@@ -169,29 +169,46 @@ __global__ void k_norm_part(const T* __restrict__ x, long long n, double* part) 
   if (threadIdx.x == 0) { part[blockIdx.x * PS] = s; part[blockIdx.x * PS + 1] = b; }
 }
 
-// grid: x = chunks of the (gx, gy) plane, y = gz, z = temporal plane; 32-bit index math
-template <class T>
+// grid: x = chunks of the (gx, gy) plane, y = gz, z = temporal plane.  The cell size is
+// compile-time, so the cell/local splits are multiply-shifts; a node reads its 1, 2, 4 or 8
+// copies with predicated loads (no divergent loops), in a fixed cell order.
+template <class T, int N, int DIM>
 __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __restrict__ cb, T* y, const T* base,
                                                      int overwrite) {
-  const int p = g.p;
+  constexpr int p = N - 1;
+  const int nn0 = g.nn[0], nn1 = g.nn[1];
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
-  if (local >= g.nn[0] * g.nn[1]) return;
-  const int gx = local % g.nn[0], gy = local / g.nn[0], gz = blockIdx.y, j = blockIdx.z;
-  const long long idx = ((long long)j * g.nn[2] + gz) * g.nn[1] * g.nn[0] + local;
-  if (gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1 ||
-      (g.dim == 3 && (gz == 0 || gz == g.nn[2] - 1))) {
+  if (local >= nn0 * nn1) return;
+  const int gy = local / nn0, gx = local - gy * nn0, gz = blockIdx.y, j = blockIdx.z;
+  const long long idx = ((long long)j * g.nn[2] + gz) * ((long long)nn1 * nn0) + local;
+  if (gx == 0 || gx == nn0 - 1 || gy == 0 || gy == nn1 - 1 || (DIM == 3 && (gz == 0 || gz == g.nn[2] - 1))) {
     if (overwrite) y[idx] = base ? base[idx] : (T)0;
     return;
   }
-  // cells containing the node along each axis (one, or two on a cell face)
-  const int x1 = gx / p, x0 = (gx % p == 0) ? x1 - 1 : x1;
-  const int y1 = gy / p, y0 = (gy % p == 0) ? y1 - 1 : y1;
-  const int z1 = g.dim == 3 ? gz / p : 0, z0 = (g.dim == 3 && gz % p == 0) ? z1 - 1 : z1;
+  // the cell whose local index range holds the node (cx, lx), and on a face also the cell below
+  // it (cx - 1, local p)
+  const int cx = gx / p, lx = gx - cx * p;
+  const int cy = gy / p, ly = gy - cy * p;
+  const int cz = DIM == 3 ? gz / p : 0, lz = DIM == 3 ? gz - cz * p : 0;
+  const long long ex = (long long)g.nc[0] * N, ey = (long long)g.nc[1] * N;
+  const long long ez = DIM == 3 ? (long long)g.nc[2] * N : 1;
   T sum = 0;
-  for (int cz = z0; cz <= z1; ++cz)
-    for (int cy = y0; cy <= y1; ++cy)
-      for (int cx = x0; cx <= x1; ++cx)
-        sum += cb[ebuf_index(g, j, cx, cy, cz, gx - cx * p, gy - cy * p, gz - cz * p)];
+#pragma unroll
+  for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz) {
+    const bool zok = DIM == 2 || zz == 1 || lz == 0;
+    const long long zrow = DIM == 3 ? (zz == 0 ? (long long)(cz - 1) * N + p : (long long)cz * N + lz) : 0;
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy) {
+      const bool yok = yy == 1 || ly == 0;
+      const long long row = (((long long)j * ez + zrow) * ey + (yy == 0 ? (long long)(cy - 1) * N + p : (long long)cy * N + ly)) * ex;
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx) {
+        const bool xok = xx == 1 || lx == 0;
+        const long long pos = row + (xx == 0 ? (long long)(cx - 1) * N + p : (long long)cx * N + lx);
+        if (zok && yok && xok) sum += cb[pos];
+      }
+    }
+  }
   if (overwrite) y[idx] = (base ? base[idx] : (T)0) + sum;
   else y[idx] += sum;
 }
@@ -205,7 +222,26 @@ template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* 
   if (plane * nz * n_t <= 0) return;
   if (plane > (1LL << 30) || nz > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the gather kernel");
   dim3 grid((unsigned)((plane + 255) / 256), (unsigned)nz, (unsigned)n_t);
-  hipLaunchKernelGGL(k_cell_gather<T>, grid, dim3(256), 0, s, g, cb, y, base, overwrite ? 1 : 0);
+  const int ow = overwrite ? 1 : 0;
+#define STMG_GATHER(NN, D) hipLaunchKernelGGL((k_cell_gather<T, NN, D>), grid, dim3(256), 0, s, g, cb, y, base, ow)
+  if (g.dim == 3) {
+    switch (g.n) {
+      case 2: STMG_GATHER(2, 3); break;
+      case 3: STMG_GATHER(3, 3); break;
+      case 4: STMG_GATHER(4, 3); break;
+      case 5: STMG_GATHER(5, 3); break;
+      default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
+    }
+  } else {
+    switch (g.n) {
+      case 2: STMG_GATHER(2, 2); break;
+      case 3: STMG_GATHER(3, 2); break;
+      case 4: STMG_GATHER(4, 2); break;
+      case 5: STMG_GATHER(5, 2); break;
+      default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
+    }
+  }
+#undef STMG_GATHER
   STMG_CHECK_LAUNCH();
 }
 template void cell_gather<double>(const GeomDesc&, int, const double*, double*, hipStream_t, const double*, bool);
