@@ -174,6 +174,7 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
       ptr.push_back((int)col.size());
     }
     T.len_out = (int)L.size();
+    T.nnz = (int)col.size();
     T.ptr = upload(ptr, s);
     T.col = upload(col, s);
     T.w64 = upload(w, s);
@@ -666,7 +667,7 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
     T* out = last ? fine : bufs[ax & 1];
     const Transfer1D& tr = F.P[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, last && accumulate, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, last && accumulate, s);
     dims[ax] = tr.len_out;
     in = out;
   }
@@ -692,7 +693,7 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
     T* out = last ? coarse : bufs[ax & 1];
     const Transfer1D& tr = F.R[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, false, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, false, s);
     dims[ax] = tr.len_out;
     in = out;
   }

@@ -14,12 +14,28 @@ namespace stmg {
 
 namespace {
 
-// grid: x = chunks of the (i0, i1) output plane, y = i2, z = temporal plane; 32-bit index math
-template <class T>
+// grid: x = chunks of the (i0, i1) output plane, y = i2, z = temporal plane; 32-bit index math.
+// STAGED: the 1D matrix (len rows, nnz entries) is copied to LDS once per block.
+template <class T, bool STAGED>
 __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __restrict__ out, int d0, int d1, int d2,
                                                int ax, int o0, int o1, const int* __restrict__ ptr,
                                                const int* __restrict__ col, const T* __restrict__ w,
-                                               int accumulate) {
+                                               int accumulate, int len, int nnz) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int* P = ptr;
+  const int* C = col;
+  const T* W = w;
+  if constexpr (STAGED) {
+    T* sw = reinterpret_cast<T*>(smem_raw);
+    int* sptr = reinterpret_cast<int*>(sw + nnz);
+    int* scol = sptr + len + 1;
+    for (int e = threadIdx.x; e <= len; e += blockDim.x) sptr[e] = ptr[e];
+    for (int e = threadIdx.x; e < nnz; e += blockDim.x) { scol[e] = col[e]; sw[e] = w[e]; }
+    __syncthreads();
+    P = sptr;
+    C = scol;
+    W = sw;
+  }
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= o0 * o1) return;
   const int i0 = local % o0, i1 = local / o0, i2 = blockIdx.y, t = blockIdx.z;
@@ -28,14 +44,14 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __re
   const long long plane_in = (long long)d0 * d1 * d2;
   const long long r = (long long)i2 * o0 * o1 + local;
   const int ia = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
+  // the input line through this output point; the contracted index moves with stride st
+  const long long st = ax == 0 ? 1 : (ax == 1 ? (long long)d0 : (long long)d0 * d1);
+  const long long line = ax == 0 ? ((long long)i2 * d1 + i1) * d0
+                                  : (ax == 1 ? (long long)i2 * d1 * d0 + i0 : (long long)i1 * d0 + i0);
+  const T* src = in + t * plane_in + line;
   T s = 0;
-  const T* src = in + t * plane_in;
-  const int k1 = ptr[ia + 1];
-  for (int k = ptr[ia]; k < k1; ++k) {
-    const int c = col[k];
-    const int j0 = ax == 0 ? c : i0, j1 = ax == 1 ? c : i1, j2 = ax == 2 ? c : i2;
-    s += w[k] * src[((long long)j2 * d1 + j1) * d0 + j0];
-  }
+  const int k1 = P[ia + 1];
+  for (int k = P[ia]; k < k1; ++k) s += W[k] * src[C[k] * st];
   T* dst = out + t * plane_out + r;
   if (accumulate) *dst += s;
   else *dst = s;
@@ -88,20 +104,25 @@ template void time_transfer<float>(const float*, int, int, long long, const unsi
 
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
-             const int* col, const T* w, bool accumulate, hipStream_t s) {
+             const int* col, const T* w, int nnz, bool accumulate, hipStream_t s) {
   const int o0 = ax == 0 ? out_len : in_dims[0], o1 = ax == 1 ? out_len : in_dims[1],
             o2 = ax == 2 ? out_len : in_dims[2];
   if ((long long)o0 * o1 * o2 * n_t <= 0) return;
   if ((long long)o0 * o1 > (1LL << 30) || o2 > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the transfer kernel");
   dim3 grid((unsigned)((o0 * o1 + 255) / 256), (unsigned)o2, (unsigned)n_t);
-  hipLaunchKernelGGL(k_sweep<T>, grid, dim3(256), 0, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax, o0, o1,
-                     ptr, col, w, accumulate ? 1 : 0);
+  const size_t lds = sizeof(T) * (size_t)nnz + sizeof(int) * (size_t)(out_len + 1 + nnz);
+  if (lds <= 16 * 1024)
+    hipLaunchKernelGGL((k_sweep<T, true>), grid, dim3(256), lds, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax,
+                       o0, o1, ptr, col, w, accumulate ? 1 : 0, out_len, nnz);
+  else
+    hipLaunchKernelGGL((k_sweep<T, false>), grid, dim3(256), 0, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax,
+                       o0, o1, ptr, col, w, accumulate ? 1 : 0, out_len, nnz);
   STMG_CHECK_LAUNCH();
 }
 
 template void sweep1d<double>(const double*, double*, int, const int*, int, int, const int*, const int*,
-                              const double*, bool, hipStream_t);
+                              const double*, int, bool, hipStream_t);
 template void sweep1d<float>(const float*, float*, int, const int*, int, int, const int*, const int*,
-                             const float*, bool, hipStream_t);
+                             const float*, int, bool, hipStream_t);
 
 }  // namespace stmg
