@@ -15,7 +15,7 @@
 namespace stmg {
 
 struct Transfer1D {           // one direction of P (coarse -> fine) or R = P^T (fine -> coarse)
-  int len_out = 0, nnz = 0;
+  int len_out = 0, nnz = 0, max_row = 0;   // rows, entries, most entries in one row
   DevBuf ptr, col, w64, w32;
 };
 

@@ -169,9 +169,11 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
     std::vector<int> ptr{0}, col;
     std::vector<double> w;
     std::vector<float> wf;
+    T.max_row = 0;
     for (auto& row : L) {
       for (auto& e : row) { col.push_back(e.first); w.push_back(e.second); wf.push_back((float)e.second); }
       ptr.push_back((int)col.size());
+      T.max_row = std::max(T.max_row, (int)row.size());
     }
     T.len_out = (int)L.size();
     T.nnz = (int)col.size();
@@ -667,7 +669,7 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
     T* out = last ? fine : bufs[ax & 1];
     const Transfer1D& tr = F.P[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, last && accumulate, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, tr.max_row, last && accumulate, s);
     dims[ax] = tr.len_out;
     in = out;
   }
@@ -693,7 +695,7 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
     T* out = last ? coarse : bufs[ax & 1];
     const Transfer1D& tr = F.R[ax];
     const T* w = std::is_same<T, double>::value ? (const T*)tr.w64.get() : (const T*)tr.w32.get();
-    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, false, s);
+    sweep1d<T>(in, out, n_t, dims, ax, tr.len_out, tr.ptr.as<int>(), tr.col.as<int>(), w, tr.nnz, tr.max_row, false, s);
     dims[ax] = tr.len_out;
     in = out;
   }

@@ -76,7 +76,7 @@ template <class T> void norm2_check(const T* x, long long n, double* out, double
 // out[.., i, ..] (+)= sum_{k in row i} w[k] * in[.., col[k], ..] with CSR (ptr, col, w).
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
-             const int* col, const T* w, int nnz, bool accumulate, hipStream_t s);
+             const int* col, const T* w, int nnz, int max_row, bool accumulate, hipStream_t s);
 
 // Temporal transfer on the interior nodes of one spatial lattice of nx nodes (transfer.hip):
 // mode 0: out = (P (x) I) in, 1: out += (P (x) I) in, 2: out = (P^T (x) I) in, with P the dense

@@ -16,7 +16,7 @@ namespace {
 
 // grid: x = chunks of the (i0, i1) output plane, y = i2, z = temporal plane; 32-bit index math.
 // STAGED: the 1D matrix (len rows, nnz entries) is copied to LDS once per block.
-template <class T, bool STAGED>
+template <class T, bool STAGED, int KMAX>
 __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __restrict__ out, int d0, int d1, int d2,
                                                int ax, int o0, int o1, const int* __restrict__ ptr,
                                                const int* __restrict__ col, const T* __restrict__ w,
@@ -50,8 +50,21 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ in, T* __re
                                   : (ax == 1 ? (long long)i2 * d1 * d0 + i0 : (long long)i1 * d0 + i0);
   const T* src = in + t * plane_in + line;
   T s = 0;
-  const int k1 = P[ia + 1];
-  for (int k = P[ia]; k < k1; ++k) s += W[k] * src[C[k] * st];
+  const int k0 = P[ia], k1 = P[ia + 1];
+  if (KMAX > 0) {
+    // at most KMAX entries per row: every load of the row is issued before the first use
+    T v[KMAX > 0 ? KMAX : 1], c[KMAX > 0 ? KMAX : 1];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const int k = k0 + q;
+      c[q] = k < k1 ? W[k] : (T)0;
+      v[q] = k < k1 ? src[C[k] * st] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) s += c[q] * v[q];
+  } else {
+    for (int k = k0; k < k1; ++k) s += W[k] * src[C[k] * st];
+  }
   T* dst = out + t * plane_out + r;
   if (accumulate) *dst += s;
   else *dst = s;
@@ -104,25 +117,35 @@ template void time_transfer<float>(const float*, int, int, long long, const unsi
 
 template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
-             const int* col, const T* w, int nnz, bool accumulate, hipStream_t s) {
+             const int* col, const T* w, int nnz, int max_row, bool accumulate, hipStream_t s) {
   const int o0 = ax == 0 ? out_len : in_dims[0], o1 = ax == 1 ? out_len : in_dims[1],
             o2 = ax == 2 ? out_len : in_dims[2];
   if ((long long)o0 * o1 * o2 * n_t <= 0) return;
   if ((long long)o0 * o1 > (1LL << 30) || o2 > 65535 || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the transfer kernel");
   dim3 grid((unsigned)((o0 * o1 + 255) / 256), (unsigned)o2, (unsigned)n_t);
   const size_t lds = sizeof(T) * (size_t)nnz + sizeof(int) * (size_t)(out_len + 1 + nnz);
-  if (lds <= 16 * 1024)
-    hipLaunchKernelGGL((k_sweep<T, true>), grid, dim3(256), lds, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax,
-                       o0, o1, ptr, col, w, accumulate ? 1 : 0, out_len, nnz);
-  else
-    hipLaunchKernelGGL((k_sweep<T, false>), grid, dim3(256), 0, s, in, out, in_dims[0], in_dims[1], in_dims[2], ax,
-                       o0, o1, ptr, col, w, accumulate ? 1 : 0, out_len, nnz);
+  const bool staged = lds <= 16 * 1024;
+  const int acc = accumulate ? 1 : 0;
+#define STMG_SWEEP(ST, K) hipLaunchKernelGGL((k_sweep<T, ST, K>), grid, dim3(256), ST ? lds : 0, s, in, out, in_dims[0], \
+                                            in_dims[1], in_dims[2], ax, o0, o1, ptr, col, w, acc, out_len, nnz)
+  if (staged) {
+    if (max_row <= 4) STMG_SWEEP(true, 4);
+    else if (max_row <= 8) STMG_SWEEP(true, 8);
+    else if (max_row <= 12) STMG_SWEEP(true, 12);
+    else STMG_SWEEP(true, 0);
+  } else {
+    if (max_row <= 4) STMG_SWEEP(false, 4);
+    else if (max_row <= 8) STMG_SWEEP(false, 8);
+    else if (max_row <= 12) STMG_SWEEP(false, 12);
+    else STMG_SWEEP(false, 0);
+  }
+#undef STMG_SWEEP
   STMG_CHECK_LAUNCH();
 }
 
 template void sweep1d<double>(const double*, double*, int, const int*, int, int, const int*, const int*,
-                              const double*, int, bool, hipStream_t);
+                              const double*, int, int, bool, hipStream_t);
 template void sweep1d<float>(const float*, float*, int, const int*, int, int, const int*, const int*,
-                             const float*, int, bool, hipStream_t);
+                             const float*, int, int, bool, hipStream_t);
 
 }  // namespace stmg
