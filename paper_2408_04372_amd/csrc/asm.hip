@@ -317,12 +317,17 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
          (DIM == 2 || (gz != 0 && gz != g.nn[2] - 1));
     node = ((long long)gz * g.nn[1] + gy) * g.nn[0] + gx;
   }
-  // P = R^T (zero padded; Dirichlet nodes read as zero)
-#pragma unroll 4
-  for (int j = j0; j < NTP; j += JSTEP) {
-    T v = 0;
-    if (in && j < n_t) v = r[(long long)j * g.nx + node];
-    P[a * LD + j] = v;
+  // P = R^T (zero padded; Dirichlet nodes read as zero); all loads issued before the stores
+  {
+    constexpr int JPT = NTP / JSTEP;
+    T v[JPT];
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj) {
+      const int j = j0 + jj * JSTEP;
+      v[jj] = (in && j < n_t) ? r[(long long)j * g.nx + node] : (T)0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj) P[a * LD + j0 + jj * JSTEP] = v[jj];
   }
   __syncthreads();
   const T* Qc = Q + (size_t)cell * NS * NS;    // column-major: Q(a, s) = Qc[s * NS + a]
@@ -413,8 +418,18 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
       for (int j = j0; j < n_t; j += JSTEP) cellbuf[e0 + j * es] = omega * P[a * LD + j];
     }
   } else if (in) {
-#pragma unroll 4
-    for (int j = j0; j < n_t; j += JSTEP) u[(long long)j * g.nx + node] += omega * P[a * LD + j];
+    constexpr int JPT = NTP / JSTEP;
+    T v[JPT];
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj) {
+      const int j = j0 + jj * JSTEP;
+      v[jj] = j < n_t ? u[(long long)j * g.nx + node] : (T)0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj) {
+      const int j = j0 + jj * JSTEP;
+      if (j < n_t) u[(long long)j * g.nx + node] = v[jj] + omega * P[a * LD + j];
+    }
   }
 }
 
