@@ -190,22 +190,47 @@ __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __rest
   const int cx = gx / p, lx = gx - cx * p;
   const int cy = gy / p, ly = gy - cy * p;
   const int cz = DIM == 3 ? gz / p : 0, lz = DIM == 3 ? gz - cz * p : 0;
-  const long long ex = (long long)g.nc[0] * N, ey = (long long)g.nc[1] * N;
-  const long long ez = DIM == 3 ? (long long)g.nc[2] * N : 1;
   T sum = 0;
+  if constexpr (N >= EBUF_CELL_MAJOR_N) {
+    // [plane][cell][local node]
+    constexpr int NQ = DIM == 3 ? N * N * N : N * N;
+    const long long nc0 = g.nc[0], nc1 = g.nc[1];
+    const long long pbase = (long long)j * g.ncells;
 #pragma unroll
-  for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz) {
-    const bool zok = DIM == 2 || zz == 1 || lz == 0;
-    const long long zrow = DIM == 3 ? (zz == 0 ? (long long)(cz - 1) * N + p : (long long)cz * N + lz) : 0;
+    for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz) {
+      const bool zok = DIM == 2 || zz == 1 || lz == 0;
+      const int czz = DIM == 3 ? (zz == 0 ? cz - 1 : cz) : 0, lzz = DIM == 3 ? (zz == 0 ? p : lz) : 0;
 #pragma unroll
-    for (int yy = 0; yy < 2; ++yy) {
-      const bool yok = yy == 1 || ly == 0;
-      const long long row = (((long long)j * ez + zrow) * ey + (yy == 0 ? (long long)(cy - 1) * N + p : (long long)cy * N + ly)) * ex;
+      for (int yy = 0; yy < 2; ++yy) {
+        const bool yok = yy == 1 || ly == 0;
+        const int cyy = yy == 0 ? cy - 1 : cy, lyy = yy == 0 ? p : ly;
 #pragma unroll
-      for (int xx = 0; xx < 2; ++xx) {
-        const bool xok = xx == 1 || lx == 0;
-        const long long pos = row + (xx == 0 ? (long long)(cx - 1) * N + p : (long long)cx * N + lx);
-        if (zok && yok && xok) sum += cb[pos];
+        for (int xx = 0; xx < 2; ++xx) {
+          const bool xok = xx == 1 || lx == 0;
+          const int cxx = xx == 0 ? cx - 1 : cx, lxx = xx == 0 ? p : lx;
+          const long long pos = (pbase + ((long long)czz * nc1 + cyy) * nc0 + cxx) * NQ + (lzz * N + lyy) * N + lxx;
+          if (zok && yok && xok) sum += cb[pos];
+        }
+      }
+    }
+  } else {
+    // broken lattice
+    const long long ex = (long long)g.nc[0] * N, ey = (long long)g.nc[1] * N;
+    const long long ez = DIM == 3 ? (long long)g.nc[2] * N : 1;
+#pragma unroll
+    for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz) {
+      const bool zok = DIM == 2 || zz == 1 || lz == 0;
+      const long long zrow = DIM == 3 ? (zz == 0 ? (long long)(cz - 1) * N + p : (long long)cz * N + lz) : 0;
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy) {
+        const bool yok = yy == 1 || ly == 0;
+        const long long row = (((long long)j * ez + zrow) * ey + (yy == 0 ? (long long)(cy - 1) * N + p : (long long)cy * N + ly)) * ex;
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) {
+          const bool xok = xx == 1 || lx == 0;
+          const long long pos = row + (xx == 0 ? (long long)(cx - 1) * N + p : (long long)cx * N + lx);
+          if (zok && yok && xok) sum += cb[pos];
+        }
       }
     }
   }

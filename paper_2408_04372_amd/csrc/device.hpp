@@ -95,12 +95,19 @@ __device__ inline long long colour_cell(const ColourSet& cs, const GeomDesc& g, 
 }
 inline int n_colours(int dim) { return dim == 3 ? 8 : 4; }
 
-// Per-cell buffer ("broken lattice"): every cell keeps its own copy of its n^d local nodes, laid
-// out as a lattice of nc * n points per direction (cell c, local node l at c * n + l), temporal
-// plane slowest.  Neighbouring cells write neighbouring runs, and a node-parallel gather reads
-// consecutive positions for consecutive nodes.
+// Per-cell buffer: every cell keeps its own copy of its n^d local nodes, temporal plane slowest.
+// For n >= 4 each cell's n^d values of a plane are contiguous ([plane][cell][local node]), so a
+// cell writes whole cache lines; for smaller cells the copies form a "broken lattice" of nc * n
+// points per direction (cell c, local node l at c * n + l), where neighbouring cells write
+// neighbouring runs and the gather reads consecutive positions for consecutive nodes.
+constexpr int EBUF_CELL_MAJOR_N = 4;
 __device__ inline long long ebuf_index(const GeomDesc& g, int j, int cx, int cy, int cz, int lx, int ly, int lz) {
   const int n = g.n;
+  if (n >= EBUF_CELL_MAJOR_N) {
+    const long long nq = g.dim == 3 ? (long long)n * n * n : (long long)n * n;
+    const long long cell = ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
+    return ((long long)j * g.ncells + cell) * nq + ((long long)lz * n + ly) * n + lx;
+  }
   const long long ex = (long long)g.nc[0] * n, ey = (long long)g.nc[1] * n;
   const long long ez = g.dim == 3 ? (long long)g.nc[2] * n : 1;
   const long long zz = g.dim == 3 ? (long long)cz * n + lz : 0;
