@@ -36,18 +36,22 @@ FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # committed FETCH_SIZE / WRITE_SIZE summaries of the finest-level kernels at the default workload
 TRAFFIC_PROFILES = {
-    "operator": (os.path.join(ROOT, "profiles", "st_apply3_heat3d_q4_dg2_c8_hbm_traffic.md"), "op_apply.hip"),
-    "smoother": (os.path.join(ROOT, "profiles", "k_asm_mfma_heat3d_q4_dg2_c8_hbm_traffic.md"), "asm.hip"),
+    "operator": (os.path.join(ROOT, "profiles", "st_apply3_heat3d_q4_dg2_c8_hbm_traffic.md"),
+                 ("op_apply.hip", "blas.hip", "device.hpp")),
+    "smoother": (os.path.join(ROOT, "profiles", "k_asm_mfma_heat3d_q4_dg2_c8_hbm_traffic.md"),
+                 ("asm.hip", "blas.hip", "device.hpp")),
 }
 
 
-def code_hash(path):
-    """sha256 (16 hex digits) of a source file with // comments and blank lines removed."""
+def code_hash(*paths):
+    """sha256 (16 hex digits) of source files with // comments and blank lines removed."""
     import hashlib
     import re
-    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in open(path).read().splitlines()]
-    text = "\n".join(ln for ln in lines if ln.strip())
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        lines = [re.sub(r"//.*", "", ln).rstrip() for ln in open(path).read().splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
+    return h.hexdigest()[:16]
 
 
 def kernel_traffic(cfg, key):
@@ -62,7 +66,7 @@ def kernel_traffic(cfg, key):
         if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_apply", "source_sha256_16"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    cur = code_hash(os.path.join(ROOT, "paper_2408_04372_amd", "csrc", src))
+    cur = code_hash(*[os.path.join(ROOT, "paper_2408_04372_amd", "csrc", f) for f in src])
     if vals.get("source_sha256_16") != cur or "traffic_bytes_per_apply" not in vals:
         return None
     return float(vals["traffic_bytes_per_apply"])
@@ -226,8 +230,8 @@ def main():
         ach, peak, unit, frac = d["GBs"], HBM_PEAK_GBS, "GB/s", d["frac_hbm"]
     else:
         ach, peak, unit, frac = d["TFLOPs"], d["peak_flops"], "TFLOP/s", d["frac_flops"]
-    roofline = {"kernel": "smoother (k_asm_mfma, finest level, 8 colour dispatches)" if dominant == "smoother"
-                else "operator (st_apply3, finest level, 8 colour dispatches)",
+    roofline = {"kernel": "smoother (k_asm_mfma over all cells + gather, finest level)" if dominant == "smoother"
+                else "operator (st_apply3 over all cells + gather, finest level)",
                 "bound": d["bound"], "achieved": ach, "peak": peak, "unit": unit, "frac": frac,
                 "traffic": kernel_traffic(cfg, dominant),
                 "avg_launch_s": d["avg_s"], "bytes_per_launch": d["bytes"], "flops_per_launch": d["flops"],
