@@ -272,14 +272,13 @@ __device__ inline void temporal_modes(T* P, int LD, const T* __restrict__ Tinv, 
   }
 }
 
-constexpr int MAXM = 2;    // M tiles per wave (NSP <= 128)
-constexpr int MAXNT = 2;    // N tiles (NTP <= 32)
+constexpr int MAXNT = 2;   // N tiles (NTP <= 32)
 constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
 
 // Same map as k_asm_apply, with both products on the matrix cores.  LDS holds one
 // [NSP][NTP + 1] panel: R^T (B operand of W = Q^T R^T), then W (B operand of Z = Q W),
-// then Z for the write-back.  Wave w owns the M tiles w, w + 4 and every N tile, and
-// loads its whole A strip (all K steps) before issuing the products.  The cell size
+// then Z for the write-back.  Wave w owns the 16-row tile w of both products and every N
+// tile, and loads its whole A strip (all K steps) before issuing the products.  The cell size
 // (DIM, N) and the padded temporal width NTP are compile-time, so every index split is a
 // multiply-shift; each thread keeps one local node and walks the temporal planes, so the
 // node offset and its Dirichlet flag are computed once.
@@ -332,14 +331,12 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
   __syncthreads();
   const T* Qc = Q + (size_t)cell * NS * NS;    // column-major: Q(a, s) = Qc[s * NS + a]
   const int li16 = lane & 15, lk = lane >> 4;
-  v4 acc[MAXM][MAXNT];
+  const int mt = wave;                          // this wave's 16-row tile of both products
+  v4 acc[MAXNT];
   // W[s][j] = sum_a Q(a, s) R^T[a][j]
 #pragma unroll
-  for (int q = 0; q < 1; ++q) {
-    const int mt = wave;
-#pragma unroll
-    for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
-    if (mt >= MT) continue;
+  for (int nt = 0; nt < NTt; ++nt) acc[nt] = v4{0, 0, 0, 0};
+  if (mt < MT) {
     const int s_idx = mt * 16 + li16;
     T av[KS];
     const T* qcol = Qc + (size_t)(s_idx < NS ? s_idx : 0) * NS;
@@ -352,18 +349,15 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
     for (int k = 0; k < KS; ++k) {
       const T* prow = P + (4 * k + lk) * LD + li16;
 #pragma unroll
-      for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
+      for (int nt = 0; nt < NTt; ++nt) acc[nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[nt]);
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 1; ++q) {
-    const int mt = wave;
-    if (mt >= MT) continue;
+  if (mt < MT) {
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
+      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[nt][rr];
   }
   __syncthreads();
   // per mode s and time cell m: W[s, m, :] <- (lambda_s M_tau + N~)^{-1} W[s, m, :]
@@ -378,11 +372,8 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
   __syncthreads();
   // Z[a][j] = sum_s Q(a, s) W[s][j]
 #pragma unroll
-  for (int q = 0; q < 1; ++q) {
-    const int mt = wave;
-#pragma unroll
-    for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = v4{0, 0, 0, 0};
-    if (mt >= MT) continue;
+  for (int nt = 0; nt < NTt; ++nt) acc[nt] = v4{0, 0, 0, 0};
+  if (mt < MT) {
     const int a_idx = mt * 16 + li16;
     T av[KS];
 #pragma unroll
@@ -394,19 +385,16 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
     for (int k = 0; k < KS; ++k) {
       const T* prow = P + (4 * k + lk) * LD + li16;
 #pragma unroll
-      for (int nt = 0; nt < NTt; ++nt) acc[q][nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[q][nt]);
+      for (int nt = 0; nt < NTt; ++nt) acc[nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[nt]);
     }
   }
   __syncthreads();
-  // Z into LDS, then added to the interior nodes
-#pragma unroll
-  for (int q = 0; q < 1; ++q) {
-    const int mt = wave;
-    if (mt >= MT) continue;
+  // Z into LDS, then added to the interior nodes (or written to this cell's buffer slot)
+  if (mt < MT) {
 #pragma unroll
     for (int nt = 0; nt < NTt; ++nt)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[q][nt][rr];
+      for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[nt][rr];
   }
   __syncthreads();
   if (cellbuf) {
@@ -514,7 +502,7 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
   if (nt_cell > 8) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs per time cell");
   size_t lds = sizeof(T) * 2 * (size_t)n_t * ns;
   const int NSP = (ns + 15) / 16 * 16, NTP = (n_t + 15) / 16 * 16;
-  const bool use_mfma = n_t >= 8 && NSP <= 16 * 4 * MAXM && NTP <= 16 * MAXNT && NSP <= 4 * MAXK &&
+  const bool use_mfma = n_t >= 8 && NSP <= 16 * 8 && NTP <= 16 * MAXNT && NSP <= 4 * MAXK &&
                         nt_cell <= 6;
   // colours of cells without shared nodes: block corrections are added without atomics
   // (with a per-cell buffer: every cell in one launch, then a node gather)
