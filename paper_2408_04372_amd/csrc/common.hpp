@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -56,6 +57,19 @@ class DevBuf {
     n_ = bytes;
     total_bytes() += (int64_t)bytes;
   }
+  // allocation that may fail without an error: returns false (and clears HIP's last error)
+  bool try_alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return true;
+    if (hipMalloc(&p_, bytes) != hipSuccess) {
+      p_ = nullptr;
+      (void)hipGetLastError();
+      return false;
+    }
+    n_ = bytes;
+    total_bytes() += (int64_t)bytes;
+    return true;
+  }
   void release() {
     if (p_) { (void)hipFree(p_); total_bytes() -= (int64_t)n_; }
     p_ = nullptr;
@@ -64,7 +78,8 @@ class DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p_); }
   void* get() const { return p_; }
   size_t bytes() const { return n_; }
-  static int64_t& total_bytes() { static int64_t t = 0; return t; }
+  // library-owned device bytes of the process (handles may be created from several threads)
+  static std::atomic<int64_t>& total_bytes() { static std::atomic<int64_t> t{0}; return t; }
 
  private:
   void* p_ = nullptr;

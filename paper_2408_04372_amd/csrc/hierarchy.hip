@@ -393,7 +393,11 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
   d.f.alloc(n);
   if (two_phase<T>(L.g.ncells)) {
     const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
-    d.cellbuf.alloc(sizeof(T) * L.g.ncells * n_t * nq);
+    const size_t bytes = sizeof(T) * L.g.ncells * n_t * nq;
+    // small levels need the buffer; on large levels it only speeds up the apply, and without
+    // it (device memory exhausted) the level runs on the colour path
+    if (L.g.ncells <= TWO_PHASE_MAX_CELLS) d.cellbuf.alloc(bytes);
+    else (void)d.cellbuf.try_alloc(bytes);
   }
   if (!coarsest) {
     d.tmpA.alloc(n);
@@ -580,7 +584,9 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     // the outer FP64 operator of the solver runs on the finest level in every mode
     if (l == 0 && !L.has64 && two_phase<double>(L.g.ncells)) {
       const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
-      L.d64.cellbuf.alloc(sizeof(double) * L.g.ncells * L.n_t() * nq);
+      const size_t bytes = sizeof(double) * L.g.ncells * L.n_t() * nq;
+      if (L.g.ncells <= TWO_PHASE_MAX_CELLS) L.d64.cellbuf.alloc(bytes);
+      else (void)L.d64.cellbuf.try_alloc(bytes);
     }
     if (!coarsest) setup_smoother(h, L);
     else setup_coarse(h, L);
