@@ -136,3 +136,20 @@ def test_temporal_prolongation_reproduces_coarse_functions(method):
             assert np.allclose(P @ np.ones(c.n_t), np.ones(cur.n_t), atol=1e-12)
         cur = c
     assert temporal.degree(cur) == (0 if method == 0 else 1) and cur.n_t // cur.nt_cell == 1
+
+
+@pytest.mark.parametrize("k,c", [(1, 4), (2, 8), (3, 2), (4, 6)])
+def test_dg_prolongation_is_galerkin(k, c):
+    # dG: trial and test spaces coincide and the coarse spaces are nested in the fine ones
+    # (Section 3.2), so the coarse slab matrices are the Galerkin products of the embedding;
+    # a wrong node, weight or cell offset in the embedding breaks this
+    s = temporal.slab(0, temporal.DG, k, c, 0.1, t0=0.5)
+    cur = s
+    levels = temporal.time_levels(s)
+    assert levels
+    for co in levels:
+        P = temporal.prolongation(cur, co)
+        for name in ("M_T", "A_T"):
+            F, C = getattr(cur, name), getattr(co, name)
+            assert np.allclose(P.T @ F @ P, C, rtol=0, atol=1e-13 * np.abs(C).max()), (name, co.n_t)
+        cur = co
