@@ -278,12 +278,21 @@ constexpr int MAXK = 32;   // K steps of 4 (NSP <= 128)
 // Same map as k_asm_apply, with both products on the matrix cores.  LDS holds one
 // [NSP][NTP + 1] panel: R^T (B operand of W = Q^T R^T), then W (B operand of Z = Q W),
 // then Z for the write-back.  Wave w owns the 16-row tile w of both products and every N
-// tile, and loads its whole A strip (all K steps) before issuing the products.  The cell size
-// (DIM, N) and the padded temporal width NTP are compile-time, so every index split is a
-// multiply-shift; each thread keeps one local node and walks the temporal planes, so the
-// node offset and its Dirichlet flag are computed once.
+// tile.  For the first product it loads the column strip Q(:, tile w) from global memory
+// (all K steps before the first product); Q is read from global memory only there.  The
+// second product needs row strips, so the column strips are handed over through two
+// [16][NSP + 1] LDS chunks: in round r every wave takes the four K steps of tile r from
+// chunk r, which wave r wrote one round earlier, while wave r + 1 fills the other chunk.
+// The K steps are taken in the same order as from global memory, so the result does not
+// depend on the hand-over.  The cell size (DIM, N) and the padded temporal width NTP are
+// compile-time, so every index split is a multiply-shift; each thread keeps one local node
+// and walks the temporal planes, so the node offset and its Dirichlet flag are computed once.
 // one wave per 16-row tile of Q (at least four waves): BT threads
 template <int NSP> constexpr int asm_threads() { return 64 * (NSP / 16 < 4 ? 4 : NSP / 16); }
+// LDS bytes: the [NSP][NTP + 1] panel and two [16][NSP + 1] chunks of Q
+template <class T, int NSP, int NTP> constexpr size_t asm_mfma_lds() {
+  return sizeof(T) * ((size_t)NSP * (NTP + 1) + 2 * 16 * (NSP + 1));
+}
 
 template <class T, int DIM, int N, int NTP>
 __global__ __launch_bounds__(512) void k_asm_mfma(
@@ -297,8 +306,10 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
   constexpr int BT = asm_threads<NSP>();
   constexpr int JSTEP = BT / NSP;
   static_assert(MT <= 8 && NTt <= MAXNT && KS <= MAXK && BT % NSP == 0, "cell too large");
+  constexpr int LDX = NSP + 1, XCH = 16 * LDX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* P = reinterpret_cast<T*>(smem_raw);    // [NSP][LD]
+  T* X = P + NSP * LD;                      // two [16][LDX] chunks of Q
   const long long li = xcd_swizzle(blockIdx.x, nblocks);
   if (li >= cs.count) return;
   int cx, cy, cz;
@@ -333,12 +344,18 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
   const int li16 = lane & 15, lk = lane >> 4;
   const int mt = wave;                          // this wave's 16-row tile of both products
   v4 acc[MAXNT];
+  // this wave's column strip: av[k] = Q(4k + lk, 16 mt + li16), zero outside the cell
+  T av[KS];
+  // chunk layout X[s - 16 w][a], rows padded to NSP + 1 so the strided writes spread over banks
+  auto put_strip = [&](T* xc) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) xc[li16 * LDX + 4 * k + lk] = av[k];
+  };
   // W[s][j] = sum_a Q(a, s) R^T[a][j]
 #pragma unroll
   for (int nt = 0; nt < NTt; ++nt) acc[nt] = v4{0, 0, 0, 0};
   if (mt < MT) {
     const int s_idx = mt * 16 + li16;
-    T av[KS];
     const T* qcol = Qc + (size_t)(s_idx < NS ? s_idx : 0) * NS;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
@@ -359,6 +376,7 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) P[(mt * 16 + Mma<T>::row(lane, rr)) * LD + nt * 16 + li16] = acc[nt][rr];
   }
+  if (wave == 0) put_strip(X);
   __syncthreads();
   // per mode s and time cell m: W[s, m, :] <- (lambda_s M_tau + N~)^{-1} W[s, m, :]
   switch (nt_cell) {
@@ -370,25 +388,24 @@ __global__ __launch_bounds__(512) void k_asm_mfma(
     default: temporal_modes<T, 6>(P, LD, Tinv, cell, NS, n_t, tid, BT); break;
   }
   __syncthreads();
-  // Z[a][j] = sum_s Q(a, s) W[s][j]
+  // Z[a][j] = sum_s Q(a, s) W[s][j]; round r takes s in tile r from chunk r % 2
 #pragma unroll
   for (int nt = 0; nt < NTt; ++nt) acc[nt] = v4{0, 0, 0, 0};
-  if (mt < MT) {
-    const int a_idx = mt * 16 + li16;
-    T av[KS];
+#pragma unroll 1
+  for (int rd = 0; rd < MT; ++rd) {
+    if (rd + 1 < MT && wave == rd + 1) put_strip(X + ((rd + 1) & 1) * XCH);
+    if (mt < MT) {
+      const T* xc = X + (rd & 1) * XCH;
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const int s_idx = 4 * k + lk;
-      av[k] = (a_idx < NS && s_idx < NS) ? Qc[(size_t)s_idx * NS + a_idx] : (T)0;
+      for (int kk = 0; kk < 4; ++kk) {
+        const T aq = xc[(4 * kk + lk) * LDX + mt * 16 + li16];
+        const T* prow = P + (16 * rd + 4 * kk + lk) * LD + li16;
+#pragma unroll
+        for (int nt = 0; nt < NTt; ++nt) acc[nt] = Mma<T>::fma(aq, prow[nt * 16], acc[nt]);
+      }
     }
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const T* prow = P + (4 * k + lk) * LD + li16;
-#pragma unroll
-      for (int nt = 0; nt < NTt; ++nt) acc[nt] = Mma<T>::fma(av[k], prow[nt * 16], acc[nt]);
-    }
+    __syncthreads();
   }
-  __syncthreads();
   // Z into LDS, then added to the interior nodes (or written to this cell's buffer slot)
   if (mt < MT) {
 #pragma unroll
@@ -427,7 +444,8 @@ void launch_asm_mfma(const GeomDesc& g, const ColourSet& cs, int n_t, int nt_cel
   constexpr int NS = DIM == 3 ? N * N * N : N * N;
   constexpr int NSP = (NS + 15) / 16 * 16;
   int nb = (int)cs.count;
-  hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(asm_threads<NSP>()), sizeof(T) * (size_t)NSP * (NTP + 1), s,
+  constexpr size_t lds = asm_mfma_lds<T, NSP, NTP>();
+  hipLaunchKernelGGL((k_asm_mfma<T, DIM, N, NTP>), dim3(nb), dim3(asm_threads<NSP>()), lds, s,
                      g, cs, n_t, nt_cell, Q, Tinv, r, u, omega, nb, cb);
 }
 
