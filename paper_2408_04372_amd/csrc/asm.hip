@@ -513,7 +513,8 @@ void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s) {
 
 template <class T>
 void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
-               T omega, hipStream_t s, T* cellbuf) {
+               T omega, hipStream_t s, T* cellbuf, bool u_zero) {
+  if (u_zero && !cellbuf) fail(STMG_E_ARG, "u_zero needs the per-cell buffer");
   int ns = (g.dim == 3) ? g.n * g.n * g.n : g.n * g.n;
   int JG = ABS / ns > 0 ? ABS / ns : 1;
   if ((n_t + JG - 1) / JG > JMAX) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs for the smoother kernel");
@@ -536,7 +537,7 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
                          omega, nb, cellbuf);
     STMG_CHECK_LAUNCH();
   }
-  if (cellbuf) cell_gather<T>(g, n_t, cellbuf, u, s);
+  if (cellbuf) cell_gather<T>(g, n_t, cellbuf, u, s, nullptr, u_zero);
 }
 
 template void asm_tinv<double>(long long, int, int, const double*, const double*, const double*, double*, int*, hipStream_t);
@@ -544,8 +545,8 @@ template void asm_tinv<float>(long long, int, int, const double*, const double*,
 template void convert_from_double<float>(const double*, float*, long long, hipStream_t);
 template void convert_from_double<double>(const double*, double*, long long, hipStream_t);
 template void asm_apply<double>(const GeomDesc&, int, int, const double*, const double*, const double*,
-                                double*, double, hipStream_t, double*);
+                                double*, double, hipStream_t, double*, bool);
 template void asm_apply<float>(const GeomDesc&, int, int, const float*, const float*, const float*, float*,
-                               float, hipStream_t, float*);
+                               float, hipStream_t, float*, bool);
 
 }  // namespace stmg

@@ -142,7 +142,8 @@ void launch_fdm(const GeomDesc& g, const ColourSet& cs, int n_t, int ntc, const 
 
 template <class T>
 void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T* fl, const T* frho,
-                   const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf) {
+                   const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf, bool u_zero) {
+  if (u_zero && !cellbuf) fail(STMG_E_ARG, "u_zero needs the per-cell buffer");
   if (nt_cell > FDM_MAXTC) fail(STMG_E_UNSUPPORTED, "too many temporal DoFs per time cell for the separable smoother");
   if ((size_t)n_t * (g.dim == 3 ? g.n * g.n * g.n : g.n * g.n) * sizeof(T) > 64 * 1024)
     fail(STMG_E_UNSUPPORTED, "cell too large for the separable smoother");
@@ -167,12 +168,12 @@ void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T
     }
     STMG_CHECK_LAUNCH();
   }
-  if (cellbuf) cell_gather<T>(g, n_t, cellbuf, u, s);
+  if (cellbuf) cell_gather<T>(g, n_t, cellbuf, u, s, nullptr, u_zero);
 }
 
 template void asm_apply_fdm<double>(const GeomDesc&, int, int, const double*, const double*, const double*,
-                                    const double*, const double*, double*, double, hipStream_t, double*);
+                                    const double*, const double*, double*, double, hipStream_t, double*, bool);
 template void asm_apply_fdm<float>(const GeomDesc&, int, int, const float*, const float*, const float*,
-                                   const float*, const float*, float*, float, hipStream_t, float*);
+                                   const float*, const float*, float*, float, hipStream_t, float*, bool);
 
 }  // namespace stmg

@@ -628,19 +628,22 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)-1, u, (T)1, r, s);
 }
 
-// u += omega * ASM(r)
-template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u) {
+// u += omega * ASM(r); u_zero: u is zero on entry (not read on the per-cell buffer path)
+template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u, bool u_zero = false) {
   LevelData<T>& d = ldata<T>(L);
+  T* cb = d.cellbuf.template as<T>();
+  if (u_zero && !cb) fill<T>(u, (T)0, L.nst(L.n_t()), h->stream);
+  u_zero = u_zero && cb;
   h->timer.mark(TB_SMOOTH, h->stream);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(1, h->stream);
   if (h->cfg.asm_variant == 1)
     asm_apply_fdm<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
-                     d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream,
-                     d.cellbuf.template as<T>());
+                     d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream, cb,
+                     u_zero);
   else
     asm_apply<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.Q.template as<T>(), d.Tinv.template as<T>(), r, u,
-                 (T)L.omega, h->stream, d.cellbuf.template as<T>());
+                 (T)L.omega, h->stream, cb, u_zero);
   if (fine) h->ktimer.end(h->stream);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)L.omega, r, (T)1, u, h->stream);
   h->timer.mark(TB_GMG, h->stream);
@@ -713,16 +716,15 @@ template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u) {
   LevelData<T>& d = ldata<T>(L);
   hipStream_t s = h->stream;
   int n_t = L.n_t();
-  long long n = L.nst(n_t);
   if (level + 1 == (int)h->levels.size()) {
     coarse_apply<T>(d.Cinv.template as<T>(), L.cidx.as<long long>(), L.cm, f, u, s);
     boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, n_t, (T)1, f, (T)0, u, s);
     return;
   }
   const int nu = h->cfg.n_smooth;
-  // pre-smoothing from u = 0: the first step needs no residual
-  fill<T>(u, (T)0, n, s);
-  asm_step<T>(h, L, f, u);
+  // pre-smoothing from u = 0: the first step needs no residual (and, on the per-cell buffer
+  // path, neither a zero fill nor a read of u)
+  asm_step<T>(h, L, f, u, true);
   for (int i = 1; i < nu; ++i) {
     residual<T>(h, L, f, u, d.r.template as<T>());
     asm_step<T>(h, L, d.r.template as<T>(), u);

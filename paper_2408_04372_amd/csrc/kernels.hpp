@@ -99,10 +99,11 @@ void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double*
               T* Tinv, int* bad, hipStream_t s);
 template <class Tout> void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s);
 // u += omega * sum_K R_K^T (I (x) Q_K) Tinv_K (I (x) Q_K^T) R_K r on interior rows.
-// cellbuf: as for st_apply (per-cell corrections, then a node gather).
+// cellbuf: as for st_apply (per-cell corrections, then a node gather).  u_zero (only with
+// cellbuf): u is taken as zero on entry and not read; the gather writes every node of u.
 template <class T>
 void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tinv, const T* r, T* u,
-               T omega, hipStream_t s, T* cellbuf = nullptr);
+               T omega, hipStream_t s, T* cellbuf = nullptr, bool u_zero = false);
 
 // Separable (fast diagonalisation) variant on Cartesian levels:
 //   u += omega * sum_K R_K^T (I (x) Q) [rho_K lambda_s M_tau + N~]^{-1} (I (x) Q^T) R_K r,
@@ -110,7 +111,8 @@ void asm_apply(const GeomDesc& g, int n_t, int nt_cell, const T* Q, const T* Tin
 // fl [3][4][n] by axis and boundary case), frho per cell, ftm = [M_tau; N~] (nt_cell^2 each).
 template <class T>
 void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T* fl, const T* frho,
-                   const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf = nullptr);
+                   const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf = nullptr,
+                   bool u_zero = false);
 
 // ---- coarse solve (coarse.hip) ---------------------------------------------------------------------
 // z[idx[i]] = sum_j Cinv[i][j] f[idx[j]] for the m interior DoFs of the coarsest level.
