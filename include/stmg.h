@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define STMG_ABI_VERSION 2
+#define STMG_ABI_VERSION 3
 
 typedef enum {
   STMG_OK = 0,
@@ -130,6 +130,8 @@ typedef struct {
   double setup_seconds;
   int32_t n_t_level[STMG_MAX_LEVELS];       /* temporal DoFs per level (differ with time_mg) */
   int32_t nt_cell_level[STMG_MAX_LEVELS];   /* temporal DoFs per time cell, per level */
+  int32_t eig_resolves;                     /* batched local eigen-solves repeated because a cell's
+                                               eigenpairs failed the check (0 normally) */
 } stmg_info;
 
 typedef struct stmg_handle stmg_handle;

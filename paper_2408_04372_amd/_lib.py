@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstmg.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_LEVELS = 16
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 5: "E_NONFINITE",
@@ -65,6 +65,7 @@ class Info(ctypes.Structure):
         ("coarse_unknowns", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
         ("setup_seconds", ctypes.c_double),
         ("n_t_level", ctypes.c_int32 * MAX_LEVELS), ("nt_cell_level", ctypes.c_int32 * MAX_LEVELS),
+        ("eig_resolves", ctypes.c_int32),
     ]
 
 
@@ -220,7 +221,8 @@ class Handle:
                 "omega": [inf.omega[i] for i in range(L)], "coarse_unknowns": inf.coarse_unknowns,
                 "device_bytes": inf.device_bytes, "setup_seconds": inf.setup_seconds,
                 "n_t_level": [inf.n_t_level[i] for i in range(L)],
-                "nt_cell_level": [inf.nt_cell_level[i] for i in range(L)]}
+                "nt_cell_level": [inf.nt_cell_level[i] for i in range(L)],
+                "eig_resolves": inf.eig_resolves}
 
     def size(self, level: int = 0) -> int:
         return self.info["n_t_level"][level] * self.info["n_x"][level]

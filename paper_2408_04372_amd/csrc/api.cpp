@@ -393,6 +393,7 @@ stmg_status stmg_query(stmg_handle* h, stmg_info* info) {
     }
     info->coarse_unknowns = h->levels.back()->cm;
     info->device_bytes = h->bytes_at_create;
+    info->eig_resolves = h->eig_resolves;
     info->setup_seconds = h->setup_seconds;
     return STMG_OK;
   });

@@ -115,6 +115,7 @@ struct stmg_handle {
   stmg::KernelTimer ktimer;
   double setup_seconds = 0.0;
   int64_t bytes_at_create = 0;
+  int eig_resolves = 0;       // batched eigen-solves repeated after a failed eigenpair check
   stmg::CnnState* cnn = nullptr;
   stmg::DevBuf vel;            // wave velocity recovery: M_T^{-1} A_T and the u0 / v0 weights
   stmg::DevBuf rhsc, rhs3x, rhs3y, rhs_mp, rhs_mc, rhs_mv, rhs_np, rhs_nc, rhs_nv;   // slab right-hand sides

@@ -98,6 +98,11 @@ template <class T>
 void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double* Mtau, const double* Nt,
               T* Tinv, int* bad, hipStream_t s);
 template <class Tout> void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s);
+// flag[c] = 1 unless cell c's eigenpairs pass: max|R - I| <= tol for R = Q^T M Q, and per column k
+// max|AQ(:, k) - lambda_k T(:, k)| <= tol (max|AQ(:, k)| + |lambda_k| max|T(:, k)|) for T = M Q
+// (column-major ns x ns blocks, ncells <= 2^31 - 1).
+void asm_eig_check(long long ncells, int ns, const double* R, const double* AQ, const double* T,
+                   const double* lam, double tol, int* flag, hipStream_t s);
 // u += omega * sum_K R_K^T (I (x) Q_K) Tinv_K (I (x) Q_K^T) R_K r on interior rows.
 // cellbuf: as for st_apply (per-cell corrections, then a node gather).  u_zero (only with
 // cellbuf): u is taken as zero on entry and not read; the gather writes every node of u.

@@ -128,6 +128,8 @@ def test_bitwise_reproducible(name):
             h.smooth(x, z, steps=2)
             h.vcycle(x, v)
             torch.cuda.synchronize()
+            # set-up repeats the batched eigen-solve only after a failed eigenpair check (rare)
+            assert 0 <= h.info["eig_resolves"] < 3
             outs.append((list(h.info["omega"]), y.cpu(), z.cpu(), v.cpu()))
         finally:
             h.close()
