@@ -124,33 +124,6 @@ __global__ void k_tinv(long long ncells, int ns, int nt, const double* __restric
   }
 }
 
-// Check of the generalised eigenpairs of a batch of cells (column-major ns x ns blocks):
-// R = Q^T M Q must be the identity and AQ = A Q must equal T Lambda with T = M Q, column by
-// column relative to max|AQ(:, k)| + |lambda_k| max|T(:, k)|.  flag[c] = 1 for a cell that fails
-// either test or holds a non-finite value.  One workgroup per cell.
-__global__ __launch_bounds__(128) void k_eig_check(int ns, const double* __restrict__ R,
-                                                   const double* __restrict__ AQ, const double* __restrict__ T,
-                                                   const double* __restrict__ lam, double tol, int* flag) {
-  const long long c = blockIdx.x;
-  const size_t off = (size_t)c * ns * ns;
-  int bad = 0;
-  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-    const double lk = lam[c * ns + k];
-    double orth = 0, an = 0, tn = 0, rr = 0;
-    for (int i = 0; i < ns; ++i) {
-      const size_t e = off + (size_t)k * ns + i;
-      orth = fmax(orth, fabs(R[e] - (i == k ? 1.0 : 0.0)));
-      an = fmax(an, fabs(AQ[e]));
-      tn = fmax(tn, fabs(T[e]));
-      rr = fmax(rr, fabs(AQ[e] - lk * T[e]));
-    }
-    // written so that a NaN anywhere fails
-    if (!(orth <= tol) || !(rr <= tol * (an + fabs(lk) * tn)) || !(fabs(lk) < 1e300)) bad = 1;
-  }
-  bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) flag[c] = bad;
-}
-
 template <class Tin, class Tout>
 __global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -518,13 +491,6 @@ void asm_extract(const GeomDesc& g, int colour, int b, const double* y, double* 
   unsigned grid = ceil_div(g.ncells * ns, 256);
   if (grid > 65536) grid = 65536;
   hipLaunchKernelGGL(k_extract, dim3(grid), dim3(256), 0, s, g, colour, b, y, Ablk, Mblk);
-  STMG_CHECK_LAUNCH();
-}
-
-void asm_eig_check(long long ncells, int ns, const double* R, const double* AQ, const double* T,
-                   const double* lam, double tol, int* flag, hipStream_t s) {
-  if (ncells <= 0) return;
-  hipLaunchKernelGGL(k_eig_check, dim3((unsigned)ncells), dim3(128), 0, s, ns, R, AQ, T, lam, tol, flag);
   STMG_CHECK_LAUNCH();
 }
 

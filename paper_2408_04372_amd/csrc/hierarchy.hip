@@ -312,6 +312,44 @@ void setup_fdm(stmg_handle* h, Level& L) {
   if (L.has32) upload_fdm<float>(L.d32, q, lam, L.rho_mean, tmat, s);
 }
 
+namespace {
+
+// Check of the generalised eigenpairs of a batch of cells (column-major ns x ns blocks):
+// R = Q^T M Q must be the identity and AQ = A Q must equal T Lambda with T = M Q, column by
+// column relative to max|AQ(:, k)| + |lambda_k| max|T(:, k)|.  flag[c] = 1 for a cell that fails
+// either test or holds a non-finite value.  One workgroup per cell.
+__global__ __launch_bounds__(128) void k_eig_check(int ns, const double* __restrict__ R,
+                                                   const double* __restrict__ AQ, const double* __restrict__ T,
+                                                   const double* __restrict__ lam, double tol, int* flag) {
+  const long long c = blockIdx.x;
+  const size_t off = (size_t)c * ns * ns;
+  int bad = 0;
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    const double lk = lam[c * ns + k];
+    double orth = 0, an = 0, tn = 0, rr = 0;
+    for (int i = 0; i < ns; ++i) {
+      const size_t e = off + (size_t)k * ns + i;
+      orth = fmax(orth, fabs(R[e] - (i == k ? 1.0 : 0.0)));
+      an = fmax(an, fabs(AQ[e]));
+      tn = fmax(tn, fabs(T[e]));
+      rr = fmax(rr, fabs(AQ[e] - lk * T[e]));
+    }
+    // written so that a NaN anywhere fails
+    if (!(orth <= tol) || !(rr <= tol * (an + fabs(lk) * tn)) || !(fabs(lk) < 1e300)) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) flag[c] = bad;
+}
+
+}  // namespace
+
+void asm_eig_check(long long ncells, int ns, const double* R, const double* AQ, const double* T,
+                   const double* lam, double tol, int* flag, hipStream_t s) {
+  if (ncells <= 0) return;
+  hipLaunchKernelGGL(k_eig_check, dim3((unsigned)ncells), dim3(128), 0, s, ns, R, AQ, T, lam, tol, flag);
+  STMG_CHECK_LAUNCH();
+}
+
 // Bound on max|Q^T M Q - I| and on the relative eigen-residual of each local eigenpair; a
 // converged FP64 solve of these blocks reaches about 1e-13 on both.
 constexpr double EIG_CHECK_TOL = 1e-8;

@@ -98,11 +98,6 @@ template <class T>
 void asm_tinv(long long ncells, int ns, int nt, const double* lam, const double* Mtau, const double* Nt,
               T* Tinv, int* bad, hipStream_t s);
 template <class Tout> void convert_from_double(const double* a, Tout* b, long long n, hipStream_t s);
-// flag[c] = 1 unless cell c's eigenpairs pass: max|R - I| <= tol for R = Q^T M Q, and per column k
-// max|AQ(:, k) - lambda_k T(:, k)| <= tol (max|AQ(:, k)| + |lambda_k| max|T(:, k)|) for T = M Q
-// (column-major ns x ns blocks, ncells <= 2^31 - 1).
-void asm_eig_check(long long ncells, int ns, const double* R, const double* AQ, const double* T,
-                   const double* lam, double tol, int* flag, hipStream_t s);
 // u += omega * sum_K R_K^T (I (x) Q_K) Tinv_K (I (x) Q_K^T) R_K r on interior rows.
 // cellbuf: as for st_apply (per-cell corrections, then a node gather).  u_zero (only with
 // cellbuf): u is taken as zero on entry and not read; the gather writes every node of u.
@@ -118,6 +113,13 @@ template <class T>
 void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T* fl, const T* frho,
                    const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf = nullptr,
                    bool u_zero = false);
+
+// ---- smoother set-up check (hierarchy.hip) ----------------------------------------------------
+// flag[c] = 1 unless cell c's eigenpairs pass: max|R - I| <= tol for R = Q^T M Q, and per column k
+// max|AQ(:, k) - lambda_k T(:, k)| <= tol (max|AQ(:, k)| + |lambda_k| max|T(:, k)|) for T = M Q
+// (column-major ns x ns blocks, ncells <= 2^31 - 1).
+void asm_eig_check(long long ncells, int ns, const double* R, const double* AQ, const double* T,
+                   const double* lam, double tol, int* flag, hipStream_t s);
 
 // ---- coarse solve (coarse.hip) ---------------------------------------------------------------------
 // z[idx[i]] = sum_j Cinv[i][j] f[idx[j]] for the m interior DoFs of the coarsest level.
