@@ -145,6 +145,9 @@ typedef struct stmg_handle stmg_handle;
  * coeff: host, one positive coefficient per finest cell (rho of eqs. heat and
  *   wave), x fastest; NULL means 1 everywhere.
  * hip_stream: a hipStream_t (NULL = default stream).
+ * The local eigenpairs of the smoother are checked after the batched solve and
+ * the solve is repeated (stmg_info.eig_resolves) when a cell fails; STMG_E_HIP
+ * if a cell still fails after three solves.
  * out: receives the handle; unchanged on failure. Synchronous. */
 stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const double* coeff,
                         void* hip_stream, stmg_handle** out);
