@@ -169,13 +169,15 @@ __global__ void k_norm_part(const T* __restrict__ x, long long n, double* part) 
   if (threadIdx.x == 0) { part[blockIdx.x * PS] = s; part[blockIdx.x * PS + 1] = b; }
 }
 
-// grid: x = chunks of the (gx, gy) plane, y = gz, z = temporal plane.  The cell size is
-// compile-time, so the cell/local splits are multiply-shifts; a node reads its 1, 2, 4 or 8
-// copies with predicated loads (no divergent loops), in a fixed cell order.
+// grid: x = chunks of the (gx, gy) plane, y = gz, z = temporal plane.  A thread forms the up to
+// 2^DIM buffer offsets of its node and their predicates, issues every load (the copies and the
+// base value) and then adds the copies in a fixed cell order (predicated loads, no divergent
+// loops).  The cell size is compile-time, so the cell/local splits are multiply-shifts.
 template <class T, int N, int DIM>
 __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __restrict__ cb, T* y, const T* base,
                                                      int overwrite) {
   constexpr int p = N - 1;
+  constexpr int NC = DIM == 3 ? 8 : 4;      // copies a node can have
   const int nn0 = g.nn[0], nn1 = g.nn[1];
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= nn0 * nn1) return;
@@ -190,7 +192,8 @@ __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __rest
   const int cx = gx / p, lx = gx - cx * p;
   const int cy = gy / p, ly = gy - cy * p;
   const int cz = DIM == 3 ? gz / p : 0, lz = DIM == 3 ? gz - cz * p : 0;
-  T sum = 0;
+  long long off[NC];
+  bool ok[NC];
   if constexpr (N >= EBUF_CELL_MAJOR_N) {
     // [plane][cell][local node]
     constexpr int NQ = DIM == 3 ? N * N * N : N * N;
@@ -206,10 +209,10 @@ __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __rest
         const int cyy = yy == 0 ? cy - 1 : cy, lyy = yy == 0 ? p : ly;
 #pragma unroll
         for (int xx = 0; xx < 2; ++xx) {
-          const bool xok = xx == 1 || lx == 0;
+          const int k = (zz * 2 + yy) * 2 + xx;
           const int cxx = xx == 0 ? cx - 1 : cx, lxx = xx == 0 ? p : lx;
-          const long long pos = (pbase + ((long long)czz * nc1 + cyy) * nc0 + cxx) * NQ + (lzz * N + lyy) * N + lxx;
-          if (zok && yok && xok) sum += cb[pos];
+          ok[k] = zok && yok && (xx == 1 || lx == 0);
+          off[k] = (pbase + ((long long)czz * nc1 + cyy) * nc0 + cxx) * NQ + (lzz * N + lyy) * N + lxx;
         }
       }
     }
@@ -227,15 +230,22 @@ __global__ __launch_bounds__(256) void k_cell_gather(GeomDesc g, const T* __rest
         const long long row = (((long long)j * ez + zrow) * ey + (yy == 0 ? (long long)(cy - 1) * N + p : (long long)cy * N + ly)) * ex;
 #pragma unroll
         for (int xx = 0; xx < 2; ++xx) {
-          const bool xok = xx == 1 || lx == 0;
-          const long long pos = row + (xx == 0 ? (long long)(cx - 1) * N + p : (long long)cx * N + lx);
-          if (zok && yok && xok) sum += cb[pos];
+          const int k = (zz * 2 + yy) * 2 + xx;
+          ok[k] = zok && yok && (xx == 1 || lx == 0);
+          off[k] = row + (xx == 0 ? (long long)(cx - 1) * N + p : (long long)cx * N + lx);
         }
       }
     }
   }
-  if (overwrite) y[idx] = (base ? base[idx] : (T)0) + sum;
-  else y[idx] += sum;
+  T v[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v[k] = ok[k] ? cb[off[k]] : (T)0;
+  const T b0 = overwrite ? (base ? base[idx] : (T)0) : y[idx];
+  T sum = 0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    if (ok[k]) sum += v[k];
+  y[idx] = b0 + sum;
 }
 
 }  // namespace
