@@ -483,7 +483,7 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
   d.u.alloc(n);
   d.r.alloc(n);
   d.f.alloc(n);
-  if (two_phase<T>(L.g.ncells)) {
+  {
     const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
     const size_t bytes = sizeof(T) * L.g.ncells * n_t * nq;
     // small levels need the buffer; on large levels it only speeds up the apply, and without
@@ -674,7 +674,7 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
     if (L.has64) alloc_work<double>(L, L.n_t(), coarsest);
     if (L.has32) alloc_work<float>(L, L.n_t(), coarsest);
     // the outer FP64 operator of the solver runs on the finest level in every mode
-    if (l == 0 && !L.has64 && two_phase<double>(L.g.ncells)) {
+    if (l == 0 && !L.has64) {
       const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
       const size_t bytes = sizeof(double) * L.g.ncells * L.n_t() * nq;
       if (L.g.ncells <= TWO_PHASE_MAX_CELLS) L.d64.cellbuf.alloc(bytes);

@@ -24,13 +24,11 @@ LevelTables make_level_tables(int p);
 template <class T>
 void st_apply(const GeomDesc& g, const LevelTables& lt, const TemporalDev<T>& tp, const T* x, T* y,
               T scale, hipStream_t s, T* cellbuf = nullptr, const T* base = nullptr, bool overwrite = false);
-// Levels with at most this many cells use the per-cell buffer path in every precision; in FP64
-// every level does (there the single launch over all cells plus a gather beats 2^d colour
-// launches with read-modify-write, in FP32 the colour path is faster on large levels).
+// Every level uses the per-cell buffer path: one launch over all cells plus a gather beats 2^d
+// colour launches with read-modify-write in both precisions.  Levels with at most this many cells
+// always allocate the buffer; larger levels allocate it best-effort and run on the colour path
+// when device memory is short.
 constexpr long long TWO_PHASE_MAX_CELLS = 4096;
-template <class T> inline bool two_phase(long long ncells) {
-  return ncells <= TWO_PHASE_MAX_CELLS || sizeof(T) == sizeof(double);
-}
 // Gather of the per-cell buffer (fixed cell order) into the lattice vector.
 // y += sum of the cell contributions (overwrite = false), or y = base + sum (overwrite = true,
 // base may be null for zero; Dirichlet nodes then receive base, or zero)
