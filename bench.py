@@ -196,7 +196,7 @@ def main():
                omega=-1.5)
     setup_s = time.time() - t0
     log(f"setup {setup_s:.1f} s, levels {h.info['n_levels']}, omega {np.round(h.info['omega'], 4).tolist()}, "
-        f"device bytes {h.info['device_bytes'] / 1e9:.1f} GB")
+        f"device bytes {h.info['device_bytes'] / 1e9:.1f} GB, eigen-solve repeats {h.info['eig_resolves']}")
     b = torch.from_numpy(si.random_slab_vector(cfg, 1001)).to(dev).reshape(-1).contiguous()
     x = torch.zeros_like(b)
     nst = h.size(0)
@@ -326,7 +326,7 @@ def main():
                    "time_method": "dG", "n_time_cells": cfg.n_time_cells, "n_st": nst,
                    "perturbation": cfg.perturb, "rtol": 1e-8, "restart": 30, "n_smooth": 1,
                    "omega_rule": "1.5/lambda_max per level",
-                   "setup_s": setup_s},
+                   "setup_s": setup_s, "eig_resolves": h.info["eig_resolves"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
