@@ -326,11 +326,12 @@ def main():
                    "time_method": "dG", "n_time_cells": cfg.n_time_cells, "n_st": nst,
                    "perturbation": cfg.perturb, "rtol": 1e-8, "restart": 30, "n_smooth": 1,
                    "omega_rule": "1.5/lambda_max per level",
-                   "setup_s": setup_s, "eig_resolves": h.info["eig_resolves"]},
+                   "setup_s": setup_s},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
     }
+    extras["eig_resolves"] = h.info["eig_resolves"]
     print(json.dumps(out), flush=True)
     h.close()
 
