@@ -412,7 +412,7 @@ void setup_smoother(stmg_handle* h, Level& L) {
   DevBuf Tb(cb), Rb(cb), AQb(cb);
   const double one = 1.0, zero = 0.0;
   const rocblas_stride bs = (rocblas_stride)ns * ns;
-  long long nbad = 0;
+  long long nbad = 0, bad_cell = -1;
   for (int attempt = 0; attempt < 3; ++attempt) {
     if (attempt > 0) {
       STMG_HIP(hipMemcpyAsync(A.get(), A0.get(), bb, hipMemcpyDeviceToDevice, s));
@@ -425,8 +425,13 @@ void setup_smoother(stmg_handle* h, Level& L) {
         info.as<int>(), (int)g.ncells);
     if (st != rocblas_status_success) fail(STMG_E_HIP, "rocsolver_dsygvj_strided_batched failed");
     std::vector<int> inf = download<int>(info.get(), g.ncells, s);
-    for (long long c = 0; c < g.ncells; ++c)
-      if (inf[c] != 0) fail(STMG_E_ARG, "local smoother block is not positive definite (cell " + std::to_string(c) + ")");
+    bad_cell = -1;
+    for (long long c = 0; c < g.ncells && bad_cell < 0; ++c)
+      if (inf[c] != 0) bad_cell = c;
+    if (bad_cell >= 0) {       // not positive definite, or not converged: also solved again
+      nbad = 1;
+      continue;
+    }
     for (long long c0 = 0; c0 < g.ncells; c0 += chunk) {
       const int nb = (int)std::min<long long>(chunk, g.ncells - c0);
       const double* Qc = A.as<double>() + c0 * ns * ns;
@@ -449,6 +454,8 @@ void setup_smoother(stmg_handle* h, Level& L) {
     for (long long c = 0; c < g.ncells; ++c) nbad += fl[c] != 0;
     if (nbad == 0) break;
   }
+  if (bad_cell >= 0)
+    fail(STMG_E_ARG, "local smoother block is not positive definite (cell " + std::to_string(bad_cell) + ")");
   if (nbad) fail(STMG_E_HIP, std::to_string(nbad) + " local eigenproblems failed the eigenpair check after 3 solves");
   A0.release();
   M0.release();
