@@ -397,11 +397,13 @@ void setup_smoother(stmg_handle* h, Level& L) {
   } rb_guard{rb};
   rocblas_set_stream(rb, s);
   // Jacobi-based batched solver: the many small problems of one level are solved in one
-  // pass each sweep (the tridiagonal route spends most of its time forming eigenvectors).
+  // pass each sweep (the tridiagonal route spends most of its time forming eigenvectors); the
+  // reduction to standard form uses batched Cholesky and triangular solves, which are much
+  // faster on these batches than the generalised solver's own column-by-column reduction.
   // Every cell's result is checked against copies of its blocks (M-orthonormality and the
-  // eigen-residual); the batched solver has been seen to return, rarely and for a single cell,
-  // a result off in the sixth digit from bitwise-identical input, so a failed check solves the
-  // batch again from the copies (at most three solves, then the set-up fails).
+  // eigen-residual); the batched generalised solver was seen to return, rarely and for a single
+  // cell, a result off in the sixth digit from bitwise-identical input, so a failed check solves
+  // the batch again from the copies (at most three solves, then the set-up fails).
   const size_t bb = sizeof(double) * (size_t)nblk;
   DevBuf A0(bb), M0(bb);
   STMG_HIP(hipMemcpyAsync(A0.get(), A.get(), bb, hipMemcpyDeviceToDevice, s));
@@ -419,15 +421,37 @@ void setup_smoother(stmg_handle* h, Level& L) {
       STMG_HIP(hipMemcpyAsync(M.get(), M0.get(), bb, hipMemcpyDeviceToDevice, s));
       ++h->eig_resolves;
     }
-    rocblas_status st = rocsolver_dsygvj_strided_batched(
-        rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, A.as<double>(), ns, bs,
-        M.as<double>(), ns, bs, 0.0, resid.as<double>(), 100, sweeps.as<int>(), lam.as<double>(), ns,
-        info.as<int>(), (int)g.ncells);
-    if (st != rocblas_status_success) fail(STMG_E_HIP, "rocsolver_dsygvj_strided_batched failed");
-    std::vector<int> inf = download<int>(info.get(), g.ncells, s);
+    // M = U^T U; C = U^{-T} A U^{-1} (two batched triangular solves, in place in A); C V = V Lambda
+    // by the batched Jacobi solver; Q = U^{-1} V, so that A Q = M Q Lambda and Q^T M Q = I
+    const int nc = (int)g.ncells;
     bad_cell = -1;
+    if (rocsolver_dpotrf_strided_batched(rb, rocblas_fill_upper, ns, M.as<double>(), ns, bs, info.as<int>(), nc) !=
+        rocblas_status_success)
+      fail(STMG_E_HIP, "rocsolver_dpotrf_strided_batched failed");
+    std::vector<int> inf = download<int>(info.get(), g.ncells, s);
     for (long long c = 0; c < g.ncells && bad_cell < 0; ++c)
       if (inf[c] != 0) bad_cell = c;
+    if (bad_cell < 0) {
+      rocblas_status t1 = rocblas_dtrsm_strided_batched(rb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                                                        rocblas_diagonal_non_unit, ns, ns, &one, M.as<double>(), ns, bs,
+                                                        A.as<double>(), ns, bs, nc);
+      rocblas_status t2 = rocblas_dtrsm_strided_batched(rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                                        rocblas_diagonal_non_unit, ns, ns, &one, M.as<double>(), ns, bs,
+                                                        A.as<double>(), ns, bs, nc);
+      rocblas_status ev = rocsolver_dsyevj_strided_batched(rb, rocblas_esort_ascending, rocblas_evect_original,
+                                                           rocblas_fill_upper, ns, A.as<double>(), ns, bs, 0.0,
+                                                           resid.as<double>(), 100, sweeps.as<int>(), lam.as<double>(),
+                                                           ns, info.as<int>(), nc);
+      rocblas_status t3 = rocblas_dtrsm_strided_batched(rb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                                                        rocblas_diagonal_non_unit, ns, ns, &one, M.as<double>(), ns, bs,
+                                                        A.as<double>(), ns, bs, nc);
+      if (t1 != rocblas_status_success || t2 != rocblas_status_success || ev != rocblas_status_success ||
+          t3 != rocblas_status_success)
+        fail(STMG_E_HIP, "batched reduction or Jacobi eigensolver failed");
+      inf = download<int>(info.get(), g.ncells, s);
+      for (long long c = 0; c < g.ncells && bad_cell < 0; ++c)
+        if (inf[c] != 0) bad_cell = c;
+    }
     if (bad_cell >= 0) {       // not positive definite, or not converged: also solved again
       nbad = 1;
       continue;
