@@ -377,15 +377,26 @@ void setup_smoother(stmg_handle* h, Level& L) {
   tp2.mptr = mp.as<int>(); tp2.mcol = mc.as<int>(); tp2.mval = mv.as<double>();
   tp2.nptr = np_.as<int>(); tp2.ncol = nc.as<int>(); tp2.nval = nv.as<double>();
   const int ncol = g.dim == 3 ? 27 : 9;
+  // the probes run on the per-cell buffer path when a buffer of two planes is at hand (the
+  // level's FP64 buffer, else a temporary one): one launch over all cells, and the gather writes
+  // every node of y2; otherwise y2 is cleared and the colour path adds to it
+  DevBuf pcb_tmp;
+  double* pcb = L.n_t() >= 2 ? L.d64.cellbuf.as<double>() : nullptr;
+  if (!pcb && pcb_tmp.try_alloc(sizeof(double) * (size_t)g.ncells * 2 * ns)) pcb = pcb_tmp.as<double>();
   fill<double>(x2.as<double>(), 0.0, 2 * g.nx, s);
   for (int colour = 0; colour < ncol; ++colour)
     for (int b = 0; b < ns; ++b) {
       asm_probe_set(g, colour, b, 1.0, x2.as<double>(), s);
-      fill<double>(y2.as<double>(), 0.0, 2 * g.nx, s);
-      st_apply<double>(g, L.lt, tp2, x2.as<double>(), y2.as<double>(), 1.0, s);
+      if (pcb) {
+        st_apply<double>(g, L.lt, tp2, x2.as<double>(), y2.as<double>(), 1.0, s, pcb, nullptr, true);
+      } else {
+        fill<double>(y2.as<double>(), 0.0, 2 * g.nx, s);
+        st_apply<double>(g, L.lt, tp2, x2.as<double>(), y2.as<double>(), 1.0, s);
+      }
       asm_extract(g, colour, b, y2.as<double>(), A.as<double>(), M.as<double>(), s);
       asm_probe_set(g, colour, b, 0.0, x2.as<double>(), s);
     }
+  pcb_tmp.release();
   x2.release();
   y2.release();
   DevBuf lam(sizeof(double) * g.ncells * ns), info(sizeof(int) * g.ncells);
