@@ -273,9 +273,13 @@ def estimate_omega(level: Level, steps: int = 15, rule: float = 0.0) -> float:
     m = steps
     for j in range(steps):
         w = asm_apply(level, level.S @ V[j])
-        for i in range(j + 1):
-            H[i, j] = V[i] @ w
-            w = w - H[i, j] * V[i]
+        # Gram-Schmidt twice: Ritz values are eigenvalue estimates only for an orthonormal
+        # basis, and one pass loses orthogonality on clustered, non-normal spectra
+        for _ in range(2):
+            for i in range(j + 1):
+                c = V[i] @ w
+                H[i, j] += c
+                w = w - c * V[i]
         H[j + 1, j] = np.linalg.norm(w)
         if H[j + 1, j] < 1e-14:
             m = j + 1

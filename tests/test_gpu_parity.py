@@ -131,7 +131,8 @@ def test_omega_estimate(name, rule):
         L = h.info["n_levels"]
         got = h.info["omega"][: L - 1]
         ref = [H.levels[L - 1 - l].omega for l in range(L - 1)]
-    # 15-step Arnoldi Ritz values are sensitive to rounding (CGS2 on the GPU vs MGS in the oracle)
+    # 15-step Arnoldi Ritz values are sensitive to rounding (both sides orthogonalise twice, in
+    # different summation orders: classical Gram-Schmidt on the GPU, modified in the oracle)
     assert np.allclose(got, ref, rtol=1e-4)
 
 

@@ -89,8 +89,9 @@ def test_vcycle_and_solve(name):
     with _handle(cfg, verts, coef, omega=-1.0, rtol=1e-12, precision=0, max_iter=300) as h:
         L = h.info["n_levels"]
         got_omega = h.info["omega"][: L - 1]
-        # 15-step Arnoldi: the top Ritz value is not converged on every level, and the rounding
-        # of CGS2 (library) and MGS (oracle) moves it in the fourth digit
+        # 15-step Arnoldi: the top Ritz value is not converged on every level, and the different
+        # summation orders of the two sides (classical Gram-Schmidt twice in the library, modified
+        # Gram-Schmidt twice in the oracle) move it in the fourth digit
         assert np.allclose(got_omega, [H.levels[L - 1 - l].omega for l in range(L - 1)], rtol=5e-3)
         assert h.info["coarse_unknowns"] == int((~H.levels[0].op.bmask).sum()) * H.levels[0].op.n_t
         for l in range(L - 1):

@@ -172,3 +172,33 @@ def test_time_multigrid_hierarchy_solves(method):
     x, it, rel = krylov.fgmres(lambda v: S @ v, b, H.vcycle, rtol=1e-12, restart=40, max_iter=200)
     assert rel <= 1e-12
     assert np.linalg.norm(x - op.solve(b).ravel()) <= 1e-9 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("problem,method,k,c,perturb", [(0, 0, 2, 1, 0.0), (1, 1, 2, 1, 0.15), (0, 0, 1, 1, 0.15)])
+def test_omega_estimate_is_exact_on_tiny_levels(problem, method, k, c, perturb):
+    # With no more interior DoFs than Arnoldi steps, the Krylov space of ASM * S (started on the
+    # interior) is the whole interior space, so the Ritz values are the eigenvalues of ASM * S
+    # there (eq. relaxation); they are compared with a dense eigen-solve of the same product
+    cfg = Config(dim=2, problem=problem, time_method=method, p=1, k=k, n_time_cells=c, n_cells=(3, 3, 1),
+                 tau=0.1, perturb=perturb, coef="lognormal", coef_sigma=0.4, seed=29)
+    op = _op(cfg)
+    lev = mg.Level(op=op, S=op.matrix())
+    lev.blocks = mg.asm_blocks(op, lev.S)
+    inner = np.flatnonzero(~np.tile(op.bmask, op.n_t))
+    assert 0 < inner.size <= 15
+    n = op.n_t * op.n_x
+    cols = []
+    for g in inner:
+        e = np.zeros(n)
+        e[g] = 1.0
+        cols.append(mg.asm_apply(lev, lev.S @ e)[inner])
+    # S is not symmetric (time stepping), so the eigenvalues come in complex pairs; the rule
+    # takes their real parts
+    ev = np.linalg.eigvals(np.array(cols).T)
+    lmax, lmin = ev.real.max(), ev.real.min()
+    assert 0.0 < lmin <= lmax
+    w_bal = 2.0 / (lmax + lmin)
+    w_top = 1.5 / lmax
+    assert mg.estimate_omega(lev, rule=0.0) == pytest.approx(min(max(w_bal, 1e-3), 1.0), rel=1e-10)
+    assert mg.estimate_omega(lev, rule=-1.5) == pytest.approx(min(max(w_top, 1e-3), 1.0), rel=1e-10)
+    assert w_top < 1.0          # the pin is not decided by the clamp
