@@ -12,8 +12,9 @@
 //     B_K^{-1} = (I (x) Q) blockdiag_s (lambda_s M_tau + N~)^{-1} (I (x) Q^T),
 // so one application per spatial cell is two dense [n_s x n_s] x [n_s x n_t]
 // products (all time cells of the slab at once) and n_s tiny N_t x N_t solves,
-// instead of a dense (N_t n_s)^2 inverse per block.  Blocks are applied in 2^d
-// colours of cells that share no node, so corrections are added without atomics.
+// instead of a dense (N_t n_s)^2 inverse per block.  Corrections are written to a
+// per-cell buffer and summed by a node gather, or, without a buffer, blocks are
+// applied in 2^d colours of cells that share no node; neither uses atomics.
 // Dirichlet nodes inside a
 // block are decoupled (identity rows in A_KK and M_KK) and masked on input and
 // output, so they never receive a correction from the block.

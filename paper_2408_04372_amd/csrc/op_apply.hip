@@ -14,10 +14,13 @@
 //   values at Gauss points by S-sweeps, reference gradients by collocation
 //   D-sweeps on the Gauss points, geometry factors (per quadrature point,
 //   computed once per cell into LDS), and the transposed sweeps back.
-// Each cell's space-time values are staged once in LDS (coalesced loads), and
-// cells are processed in 2^d colours of cells that share no node, so every
-// contribution is added with a plain read-modify-write (no atomics; results are
-// bitwise reproducible).  In 2D a team is a single lane holding the whole cell.
+// Each cell's space-time values are staged once in LDS (coalesced loads).  With a
+// per-cell buffer, one launch covers every cell and each cell writes its
+// contribution to its own slot, which a node gather then sums in a fixed cell
+// order; without one, cells are processed in 2^d colours of cells that share no
+// node and every contribution is added with a plain read-modify-write.  Neither
+// path uses atomics, so results are bitwise reproducible.  In 2D a team is a
+// single lane holding the whole cell.
 #include "device.hpp"
 #include "kernels.hpp"
 
