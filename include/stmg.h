@@ -289,6 +289,28 @@ void stmg_destroy(stmg_handle* h);
 /* Message of the last failing call on this thread ("" if none). */
 const char* stmg_last_error(void);
 
+/* Host only (no device work, no handle): the slab temporal matrices the library
+ * builds (Sections 2.1-2.2; dG on right-Radau nodes, eq. dg-time-weights; cGP on
+ * Gauss-Lobatto nodes with the last k test functions, eq. cg-time-weights).
+ * problem 0 heat / 1 wave, method 0 dG / 1 cGP, k as in stmg_config, n_time_cells
+ * time cells of length tau > 0.  n_t receives n_time_cells * (k + 1) (dG) or
+ * n_time_cells * k (cGP).  M_T, A_T, N_T: host, row-major n_t x n_t, each written
+ * when non-NULL (N_T = A_T for heat, A_T M_T^{-1} A_T for wave); cap is the
+ * capacity of each in doubles.  STMG_E_ARG / STMG_E_UNSUPPORTED for invalid
+ * parameters or cap < n_t * n_t (nothing written then). */
+stmg_status stmg_temporal_matrices(int problem, int method, int k, int n_time_cells, double tau, int64_t cap,
+                                   int32_t* n_t, double* M_T, double* A_T, double* N_T);
+
+/* Host only: the temporal prolongation between two discretisations of one slab
+ * of length slab_length (Section 3.2: the coarse trial functions evaluated at
+ * the fine DoF times; restriction is its transpose), as used between temporal
+ * levels with time_mg.  The coarse space must lie in the fine one:
+ * k_coarse <= k_fine and c_coarse divides c_fine (STMG_E_ARG otherwise).  rows,
+ * cols receive the fine and coarse n_t; P (host, row-major rows x cols, capacity
+ * cap doubles) is written when non-NULL. */
+stmg_status stmg_temporal_prolongation(int problem, int method, int k_fine, int c_fine, int k_coarse, int c_coarse,
+                                       double slab_length, int64_t cap, int32_t* rows, int32_t* cols, double* P);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,12 @@ _SIGS = {
                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "stmg_destroy": ([ctypes.c_void_p], None),
     "stmg_last_error": ([], ctypes.c_char_p),
+    "stmg_temporal_matrices": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p], ctypes.c_int),
+    "stmg_temporal_prolongation": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p], ctypes.c_int),
 }
 
 
@@ -142,6 +148,32 @@ def _check(code: int):
     if code != 0:
         msg = load().stmg_last_error().decode(errors="replace")
         raise StmgError(code, msg)
+
+
+def temporal_matrices(problem: int, method: int, k: int, n_time_cells: int, tau: float):
+    """(M_T, A_T, N_T) as the library builds them (host only; numpy arrays, n_t x n_t)."""
+    import numpy as np
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.stmg_temporal_matrices(problem, method, k, n_time_cells, tau, 0, ctypes.byref(n), None, None, None))
+    out = [np.empty((n.value, n.value)) for _ in range(3)]
+    _check(lib.stmg_temporal_matrices(problem, method, k, n_time_cells, tau, n.value * n.value, ctypes.byref(n),
+                                      *[ctypes.c_void_p(a.ctypes.data) for a in out]))
+    return tuple(out)
+
+
+def temporal_prolongation(problem: int, method: int, k_fine: int, c_fine: int, k_coarse: int, c_coarse: int,
+                          slab_length: float):
+    """Temporal prolongation fine n_t x coarse n_t as the library builds it (host only)."""
+    import numpy as np
+    lib = load()
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    args = (problem, method, k_fine, c_fine, k_coarse, c_coarse, slab_length)
+    _check(lib.stmg_temporal_prolongation(*args, 0, ctypes.byref(r), ctypes.byref(c), None))
+    P = np.empty((r.value, c.value))
+    _check(lib.stmg_temporal_prolongation(*args, P.size, ctypes.byref(r), ctypes.byref(c),
+                                          ctypes.c_void_p(P.ctypes.data)))
+    return P
 
 
 def c_config(cfg, **overrides) -> CConfig:

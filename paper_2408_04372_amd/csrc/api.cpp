@@ -1,6 +1,7 @@
 // C ABI entry points of libstmg (declared in include/stmg.h).  Every entry
 // point validates its arguments, runs the C++ implementation and converts any
 // exception into an stmg_status plus a thread-local message.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -64,6 +65,17 @@ void check_config(const stmg_config* c) {
   int per = c->time_method == STMG_DG ? c->k + 1 : c->k;
   long long nst = nx * per * c->n_time_cells;
   if (nst >= (1LL << 31)) fail(STMG_E_UNSUPPORTED, "more than 2^31 space-time DoFs");
+}
+
+// the temporal parameters the library supports (the same limits as stmg_create)
+void check_temporal(int problem, int method, int k, int c, double tau) {
+  using stmg::fail;
+  if (problem != STMG_HEAT && problem != STMG_WAVE) fail(STMG_E_ARG, "problem must be heat (0) or wave (1)");
+  if (method != STMG_DG && method != STMG_CGP) fail(STMG_E_ARG, "method must be dG (0) or cGP (1)");
+  if (method == STMG_DG && (k < 0 || k > 5)) fail(STMG_E_UNSUPPORTED, "dG degree k must be in 0..5");
+  if (method == STMG_CGP && (k < 1 || k > 5)) fail(STMG_E_UNSUPPORTED, "cGP degree k must be in 1..5");
+  if (c < 1 || c > 4096) fail(STMG_E_ARG, "the number of time cells must be in 1..4096");
+  if (!(tau > 0.0) || !std::isfinite(tau)) fail(STMG_E_ARG, "tau must be positive");
 }
 
 // every multilinear cell must have a positive Jacobian determinant at its corners
@@ -404,6 +416,47 @@ void stmg_destroy(stmg_handle* h) {
     delete h;
   } catch (...) {
   }
+}
+
+stmg_status stmg_temporal_matrices(int problem, int method, int k, int n_time_cells, double tau, int64_t cap,
+                                   int32_t* n_t, double* M_T, double* A_T, double* N_T) {
+  return guarded([&] {
+    check_temporal(problem, method, k, n_time_cells, tau);
+    if (!n_t) stmg::fail(STMG_E_ARG, "n_t is NULL");
+    const stmg::hm::Temporal T = stmg::hm::temporal(problem, method, k, n_time_cells, tau);
+    *n_t = T.n_t;
+    const stmg::hm::Mat* src[3] = {&T.M_T, &T.A_T, &T.N_T};
+    double* dst[3] = {M_T, A_T, N_T};
+    for (int m = 0; m < 3; ++m) {
+      if (!dst[m]) continue;
+      if (cap < (int64_t)T.n_t * T.n_t) stmg::fail(STMG_E_ARG, "cap is smaller than n_t * n_t");
+      std::copy(src[m]->a.begin(), src[m]->a.end(), dst[m]);
+    }
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_temporal_prolongation(int problem, int method, int k_fine, int c_fine, int k_coarse, int c_coarse,
+                                       double slab_length, int64_t cap, int32_t* rows, int32_t* cols, double* P) {
+  return guarded([&] {
+    if (!(slab_length > 0.0) || !std::isfinite(slab_length)) stmg::fail(STMG_E_ARG, "slab_length must be positive");
+    if (c_fine < 1 || c_coarse < 1) stmg::fail(STMG_E_ARG, "time cell counts must be >= 1");
+    check_temporal(problem, method, k_fine, c_fine, slab_length / c_fine);
+    check_temporal(problem, method, k_coarse, c_coarse, slab_length / c_coarse);
+    if (k_coarse > k_fine || c_fine % c_coarse != 0)
+      stmg::fail(STMG_E_ARG, "the coarse temporal space must lie in the fine one (k_coarse <= k_fine, c_coarse divides c_fine)");
+    if (!rows || !cols) stmg::fail(STMG_E_ARG, "rows or cols is NULL");
+    const stmg::hm::Temporal F = stmg::hm::temporal(problem, method, k_fine, c_fine, slab_length / c_fine);
+    const stmg::hm::Temporal C = stmg::hm::temporal(problem, method, k_coarse, c_coarse, slab_length / c_coarse);
+    const stmg::hm::Mat Pm = stmg::hm::temporal_prolongation(F, C);
+    *rows = Pm.r;
+    *cols = Pm.c;
+    if (P) {
+      if (cap < (int64_t)Pm.r * Pm.c) stmg::fail(STMG_E_ARG, "cap is smaller than rows * cols");
+      std::copy(Pm.a.begin(), Pm.a.end(), P);
+    }
+    return STMG_OK;
+  });
 }
 
 const char* stmg_last_error(void) { return g_last_error.c_str(); }
