@@ -301,6 +301,15 @@ const char* stmg_last_error(void);
 stmg_status stmg_temporal_matrices(int problem, int method, int k, int n_time_cells, double tau, int64_t cap,
                                    int32_t* n_t, double* M_T, double* A_T, double* N_T);
 
+/* Host only: the temporal factors of the smoother's local blocks (Section 3.3,
+ * eq. vanka0: every time cell of the slab has the same block M_tau (x) A_KK +
+ * N~ (x) M_KK, with M_tau and N~ the diagonal time-cell blocks of M_T and N_T).
+ * Arguments as for stmg_temporal_matrices, for one time cell of length tau;
+ * nt_cell receives k + 1 (dG) or k (cGP); M_tau, N_tilde: host, row-major
+ * nt_cell x nt_cell, written when non-NULL (capacity cap doubles each). */
+stmg_status stmg_temporal_cell_factors(int problem, int method, int k, double tau, int64_t cap, int32_t* nt_cell,
+                                       double* M_tau, double* N_tilde);
+
 /* Host only: the temporal prolongation between two discretisations of one slab
  * of length slab_length (Section 3.2: the coarse trial functions evaluated at
  * the fine DoF times; restriction is its transpose), as used between temporal

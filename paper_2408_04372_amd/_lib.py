@@ -118,6 +118,8 @@ _SIGS = {
     "stmg_temporal_matrices": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p], ctypes.c_int),
+    "stmg_temporal_cell_factors": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "stmg_temporal_prolongation": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p], ctypes.c_int),
@@ -159,6 +161,18 @@ def temporal_matrices(problem: int, method: int, k: int, n_time_cells: int, tau:
     out = [np.empty((n.value, n.value)) for _ in range(3)]
     _check(lib.stmg_temporal_matrices(problem, method, k, n_time_cells, tau, n.value * n.value, ctypes.byref(n),
                                       *[ctypes.c_void_p(a.ctypes.data) for a in out]))
+    return tuple(out)
+
+
+def temporal_cell_factors(problem: int, method: int, k: int, tau: float):
+    """(M_tau, N_tilde) of the smoother's local blocks as the library builds them (host only)."""
+    import numpy as np
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.stmg_temporal_cell_factors(problem, method, k, tau, 0, ctypes.byref(n), None, None))
+    out = [np.empty((n.value, n.value)) for _ in range(2)]
+    _check(lib.stmg_temporal_cell_factors(problem, method, k, tau, n.value * n.value, ctypes.byref(n),
+                                          *[ctypes.c_void_p(a.ctypes.data) for a in out]))
     return tuple(out)
 
 

@@ -436,6 +436,24 @@ stmg_status stmg_temporal_matrices(int problem, int method, int k, int n_time_ce
   });
 }
 
+stmg_status stmg_temporal_cell_factors(int problem, int method, int k, double tau, int64_t cap, int32_t* nt_cell,
+                                       double* M_tau, double* N_tilde) {
+  return guarded([&] {
+    check_temporal(problem, method, k, 1, tau);
+    if (!nt_cell) stmg::fail(STMG_E_ARG, "nt_cell is NULL");
+    const stmg::hm::Temporal T = stmg::hm::temporal(problem, method, k, 1, tau);
+    *nt_cell = T.nt_cell;
+    const stmg::hm::Mat* src[2] = {&T.M_tau, &T.N_tilde};
+    double* dst[2] = {M_tau, N_tilde};
+    for (int m = 0; m < 2; ++m) {
+      if (!dst[m]) continue;
+      if (cap < (int64_t)T.nt_cell * T.nt_cell) stmg::fail(STMG_E_ARG, "cap is smaller than nt_cell * nt_cell");
+      std::copy(src[m]->a.begin(), src[m]->a.end(), dst[m]);
+    }
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_temporal_prolongation(int problem, int method, int k_fine, int c_fine, int k_coarse, int c_coarse,
                                        double slab_length, int64_t cap, int32_t* rows, int32_t* cols, double* P) {
   return guarded([&] {

@@ -62,3 +62,19 @@ def test_host_queries_reject_bad_arguments():
         L.temporal_prolongation(0, 0, 1, 4, 2, 2, 1.0)  # coarse degree above fine
     with pytest.raises(L.StmgError):
         L.temporal_prolongation(0, 0, 1, 4, 1, 3, 1.0)  # 3 does not divide 4
+
+
+@pytest.mark.parametrize("problem", [0, 1])
+@pytest.mark.parametrize("method,k", [(0, 0), (0, 2), (1, 1), (1, 3)])
+def test_smoother_temporal_factors_are_the_diagonal_time_cell_blocks(problem, method, k):
+    # every time cell's local block of the smoother uses the diagonal time-cell blocks of M_T and
+    # N_T (eq. vanka0); they are the same for every cell of the slab
+    tau, c = 0.04, 4
+    Mt, Nt = _lib().temporal_cell_factors(problem, method, k, tau)
+    s = temporal.slab(problem, method, k, c, tau)
+    n = s.nt_cell
+    assert Mt.shape == (n, n)
+    for m in range(c):
+        blk = slice(m * n, (m + 1) * n)
+        assert np.allclose(Mt, s.M_T[blk, blk], rtol=1e-12, atol=1e-14)
+        assert np.allclose(Nt, s.N_T[blk, blk], rtol=1e-12, atol=1e-13 * np.abs(s.N_T).max())
