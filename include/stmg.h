@@ -301,6 +301,18 @@ const char* stmg_last_error(void);
 stmg_status stmg_temporal_matrices(int problem, int method, int k, int n_time_cells, double tau, int64_t cap,
                                    int32_t* n_t, double* M_T, double* A_T, double* N_T);
 
+/* Host only: the 1D factor of the spatial prolongation along one axis (Section
+ * 3.2: the coarse Q_p function evaluated at the fine Gauss-Lobatto nodes; the
+ * prolongation on a tensor lattice is the Kronecker product of the axis factors,
+ * applied to every temporal plane), from p_coarse on n_coarse cells to p_fine on
+ * n_fine cells of the same interval, as the level transfers use it: rows and
+ * columns of the two Dirichlet end nodes are zero.  Requires p_coarse <= p_fine
+ * and n_coarse dividing n_fine.  rows, cols receive p_fine n_fine + 1 and
+ * p_coarse n_coarse + 1; P (host, row-major, capacity cap doubles) is written
+ * when non-NULL. */
+stmg_status stmg_transfer_1d(int p_coarse, int n_coarse, int p_fine, int n_fine, int64_t cap, int32_t* rows,
+                             int32_t* cols, double* P);
+
 /* Host only: the temporal factors of the smoother's local blocks (Section 3.3,
  * eq. vanka0: every time cell of the slab has the same block M_tau (x) A_KK +
  * N~ (x) M_KK, with M_tau and N~ the diagonal time-cell blocks of M_T and N_T).

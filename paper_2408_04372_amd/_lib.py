@@ -120,6 +120,9 @@ _SIGS = {
                                 ctypes.c_void_p], ctypes.c_int),
     "stmg_temporal_cell_factors": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "stmg_transfer_1d": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
+                         ctypes.c_int),
     "stmg_temporal_prolongation": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p], ctypes.c_int),
@@ -174,6 +177,18 @@ def temporal_cell_factors(problem: int, method: int, k: int, tau: float):
     _check(lib.stmg_temporal_cell_factors(problem, method, k, tau, n.value * n.value, ctypes.byref(n),
                                           *[ctypes.c_void_p(a.ctypes.data) for a in out]))
     return tuple(out)
+
+
+def transfer_1d(p_coarse: int, n_coarse: int, p_fine: int, n_fine: int):
+    """1D factor of the spatial prolongation (Dirichlet end rows and columns zero; host only)."""
+    import numpy as np
+    lib = load()
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    args = (p_coarse, n_coarse, p_fine, n_fine)
+    _check(lib.stmg_transfer_1d(*args, 0, ctypes.byref(r), ctypes.byref(c), None))
+    P = np.empty((r.value, c.value))
+    _check(lib.stmg_transfer_1d(*args, P.size, ctypes.byref(r), ctypes.byref(c), ctypes.c_void_p(P.ctypes.data)))
+    return P
 
 
 def temporal_prolongation(problem: int, method: int, k_fine: int, c_fine: int, k_coarse: int, c_coarse: int,

@@ -454,6 +454,29 @@ stmg_status stmg_temporal_cell_factors(int problem, int method, int k, double ta
   });
 }
 
+stmg_status stmg_transfer_1d(int p_coarse, int n_coarse, int p_fine, int n_fine, int64_t cap, int32_t* rows,
+                             int32_t* cols, double* P) {
+  return guarded([&] {
+    using stmg::fail;
+    if (p_coarse < 1 || p_coarse > 4 || p_fine < 1 || p_fine > 4) fail(STMG_E_UNSUPPORTED, "p must be in 1..4");
+    if (n_coarse < 1 || n_fine < 1 || n_fine > (1 << 20)) fail(STMG_E_ARG, "cell counts must be in 1..2^20");
+    if (p_coarse > p_fine || n_fine % n_coarse != 0)
+      fail(STMG_E_ARG, "the coarse space must lie in the fine one (p_coarse <= p_fine, n_coarse divides n_fine)");
+    if (!rows || !cols) fail(STMG_E_ARG, "rows or cols is NULL");
+    const int nf = p_fine * n_fine + 1, nc = p_coarse * n_coarse + 1;
+    *rows = nf;
+    *cols = nc;
+    if (P) {
+      if (cap < (int64_t)nf * nc) fail(STMG_E_ARG, "cap is smaller than rows * cols");
+      std::fill(P, P + (size_t)nf * nc, 0.0);
+      const auto L = stmg::transfer_1d_rows(p_coarse, n_coarse, p_fine, n_fine);
+      for (int g = 0; g < nf; ++g)
+        for (const auto& e : L[g]) P[(size_t)g * nc + e.first] = e.second;
+    }
+    return STMG_OK;
+  });
+}
+
 stmg_status stmg_temporal_prolongation(int problem, int method, int k_fine, int c_fine, int k_coarse, int c_coarse,
                                        double slab_length, int64_t cap, int32_t* rows, int32_t* cols, double* P) {
   return guarded([&] {

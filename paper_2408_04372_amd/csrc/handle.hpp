@@ -6,6 +6,7 @@
 
 #include <array>
 #include <memory>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -139,6 +140,10 @@ void node_coordinates(stmg_handle* h, double* xyz);
 void point_values(stmg_handle* h, const double* U, int n_planes, int npts, const double* pts, double* out);
 // CSR of the nonzeros of a dense matrix (hierarchy.hip)
 template <class T> int upload_csr(const hm::Mat& A, DevBuf& ptr, DevBuf& col, DevBuf& val, hipStream_t s);
+// Rows of the 1D prolongation from a coarse (pc, ncc cells) to a fine (pf, ncf cells) lattice along
+// one axis, interior nodes only (first and last rows and columns dropped): rows[g] lists
+// (coarse node, weight) in increasing coarse node order.  Host only.
+std::vector<std::vector<std::pair<int, double>>> transfer_1d_rows(int pc, int ncc, int pf, int ncf);
 // learned stage (cnn.hip)
 void cnn_create(stmg_handle* h, int n_layers, const int* channels);
 long long cnn_param_count(stmg_handle* h);

@@ -139,15 +139,17 @@ void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {
   tb.dev.nptr = tb.nptr.template as<int>(); tb.dev.ncol = tb.ncol.template as<int>(); tb.dev.nval = tb.nval.template as<T>();
 }
 
+}  // namespace
+
 // 1D prolongation from a coarse (pc, ncc cells) to a fine (pf, ncf cells) lattice along one axis
 // The transfers act on interior nodes only (P_full = M_f P M_c with the interior indicators
 // M); the indicator of a tensor lattice is the product of per-axis indicators, so it is
 // folded into the 1D factors: first and last rows and columns are dropped.
-void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R, hipStream_t s) {
+std::vector<std::vector<std::pair<int, double>>> transfer_1d_rows(int pc, int ncc, int pf, int ncf) {
   int r = ncf / ncc;
   int Nf = pf * ncf + 1, Nc = pc * ncc + 1;
   hm::Vec fn = hm::gauss_lobatto(pf + 1), cn = hm::gauss_lobatto(pc + 1);
-  std::vector<std::vector<std::pair<int, double>>> rows(Nf), cols(Nc);
+  std::vector<std::vector<std::pair<int, double>>> rows(Nf);
   for (int g = 0; g < Nf; ++g) {
     int cf = std::min(g / pf, ncf - 1);
     int lf = g - cf * pf;
@@ -162,9 +164,19 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
       const int c = cc * pc + j;
       if (c == 0 || c == Nc - 1) continue;                // Dirichlet coarse node
       rows[g].push_back({cc * pc + j, w});
-      cols[cc * pc + j].push_back({g, w});
     }
   }
+  return rows;
+}
+
+namespace {
+
+void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R, hipStream_t s) {
+  const std::vector<std::vector<std::pair<int, double>>> rows = transfer_1d_rows(pc, ncc, pf, ncf);
+  // R = P^T, each column's entries in increasing fine index
+  std::vector<std::vector<std::pair<int, double>>> cols(pc * ncc + 1);
+  for (int g = 0; g < (int)rows.size(); ++g)
+    for (auto& e : rows[g]) cols[e.first].push_back({g, e.second});
   auto up = [&](const std::vector<std::vector<std::pair<int, double>>>& L, Transfer1D& T) {
     std::vector<int> ptr{0}, col;
     std::vector<double> w;

@@ -1,7 +1,8 @@
-"""The library's host-side temporal set-up (C++) against the oracle (Python), on the CPU: slab
-matrices M_T, A_T, N_T for both problems and both methods (Sections 2.1-2.2), and the temporal
-prolongations between the k- and tau-levels of the temporal hierarchy (Section 3.2).  The two
-implementations share no code; the library calls are host only."""
+"""The library's host-side set-up (C++) against the oracle (Python), on the CPU: slab matrices
+M_T, A_T, N_T for both problems and both methods (Sections 2.1-2.2), the smoother's temporal cell
+factors (Section 3.3), the temporal prolongations between the k- and tau-levels and the 1D
+factors of the spatial p- and h-prolongations (Section 3.2).  The two implementations share no
+code; the library calls are host only."""
 import os
 
 import numpy as np
@@ -78,3 +79,44 @@ def test_smoother_temporal_factors_are_the_diagonal_time_cell_blocks(problem, me
         blk = slice(m * n, (m + 1) * n)
         assert np.allclose(Mt, s.M_T[blk, blk], rtol=1e-12, atol=1e-14)
         assert np.allclose(Nt, s.N_T[blk, blk], rtol=1e-12, atol=1e-13 * np.abs(s.N_T).max())
+
+
+def _interior(space):
+    """Interior flags of a tensor lattice, x fastest."""
+    flags = [np.r_[False, np.ones(n - 2, bool), False] for n in space.nodes]
+    out = flags[0]
+    for f in flags[1:]:
+        out = np.kron(f, out).astype(bool)
+    return out
+
+
+@pytest.mark.parametrize("dim,p,cells,perturb", [(2, 4, (4, 4, 1), 0.0), (3, 3, (4, 2, 2), 0.1), (2, 2, (6, 3, 1), 0.1)])
+def test_spatial_transfer_factors_match_oracle(dim, p, cells, perturb):
+    # the library prolongs by the Kronecker product of its 1D axis factors (Dirichlet rows and
+    # columns dropped); on interior nodes that equals the oracle's assembled prolongation between
+    # consecutive levels (p-halving, then h-halving)
+    from oracle import mg, spacetime
+    from stmg_inputs import Config, draw_problem
+    cfg = Config(dim=dim, problem=0, time_method=0, p=p, k=0, n_time_cells=1, n_cells=cells, tau=0.1,
+                 perturb=perturb, seed=31)
+    verts, coef = draw_problem(cfg)
+    spaces = mg.level_spaces(spacetime.from_config(cfg, verts, coef).space)
+    assert len(spaces) >= 2
+    for fine, coarse in zip(spaces[:-1], spaces[1:]):
+        factors = [_lib().transfer_1d(coarse.p, coarse.cells[d], fine.p, fine.cells[d]) for d in range(dim)]
+        P = factors[0]
+        for f in factors[1:]:
+            P = np.kron(f, P)
+        ref = mg.prolongation(coarse, fine).toarray()
+        fi, ci = _interior(fine), _interior(coarse)
+        assert P.shape == ref.shape
+        assert np.allclose(P[np.ix_(fi, ci)], ref[np.ix_(fi, ci)], rtol=0, atol=1e-13)
+        assert not P[~fi].any() and not P[:, ~ci].any()
+
+
+def test_transfer_1d_rejects_non_nested_pairs():
+    L = _lib()
+    with pytest.raises(L.StmgError):
+        L.transfer_1d(2, 4, 1, 4)          # coarse degree above fine
+    with pytest.raises(L.StmgError):
+        L.transfer_1d(1, 3, 1, 4)          # 3 does not divide 4
