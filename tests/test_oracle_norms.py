@@ -1,0 +1,42 @@
+"""Pins of the oracle's L2(L2) error (eq. norms): the discrete solution that interpolates a
+space-time polynomial of the discrete degrees has zero error, and the error of the zero solution
+is the closed-form norm of the exact function."""
+import numpy as np
+import pytest
+
+from oracle import norms, spacetime, spatial, temporal
+from stmg_inputs import Config, draw_problem
+
+
+def _op(method, p, k, c, cells=(3, 2, 1)):
+    cfg = Config(dim=2, problem=0, time_method=method, p=p, k=k, n_time_cells=c, n_cells=cells, tau=0.25,
+                 t0=0.5, perturb=0.0, seed=3)
+    verts, coef = draw_problem(cfg)
+    return cfg, spacetime.from_config(cfg, verts, coef)
+
+
+@pytest.mark.parametrize("method,p,k", [(0, 2, 2), (0, 3, 1), (1, 2, 2), (1, 1, 3)])
+def test_interpolant_of_discrete_polynomial_has_zero_error(method, p, k):
+    cfg, op = _op(method, p, k, 3)
+    # degree p in each space direction, degree k (dG) or k (cGP trial degree) in time
+    tk = k
+    u = lambda x, t: (1.0 + x[..., 0] - 0.7 * x[..., 0] ** p) * (0.5 + x[..., 1] ** p) * (1.0 + 0.3 * t ** tk - t)
+    X = spatial.node_coordinates(op.space)
+    U = np.stack([u(X, t) for t in op.slab.times])
+    u0 = u(X, cfg.t0) if method == 1 else None
+    scale = norms.l2l2_error(op, np.zeros_like(U), u, k, u0=None if method == 0 else np.zeros(op.n_x))
+    err = norms.l2l2_error(op, U, u, k, u0=u0)
+    assert scale > 0.1
+    assert err < 1e-12 * scale
+
+
+@pytest.mark.parametrize("method,k", [(0, 1), (1, 2)])
+def test_zero_solution_error_is_the_exact_norm(method, k):
+    cfg, op = _op(method, 2, k, 4)
+    lo, hi = np.array(cfg.lo[:2], float), np.array(cfg.hi[:2], float)
+    t0, t1 = cfg.t0, cfg.t0 + cfg.n_time_cells * cfg.tau
+    u = lambda x, t: x[..., 0] * t
+    exact = np.sqrt((hi[0] ** 3 - lo[0] ** 3) / 3.0 * (hi[1] - lo[1]) * (t1 ** 3 - t0 ** 3) / 3.0)
+    U = np.zeros((op.n_t, op.n_x))
+    got = norms.l2l2_error(op, U, u, k, u0=np.zeros(op.n_x) if method == 1 else None)
+    assert got == pytest.approx(exact, rel=1e-13)
