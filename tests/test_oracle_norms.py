@@ -40,3 +40,17 @@ def test_zero_solution_error_is_the_exact_norm(method, k):
     U = np.zeros((op.n_t, op.n_x))
     got = norms.l2l2_error(op, U, u, k, u0=np.zeros(op.n_x) if method == 1 else None)
     assert got == pytest.approx(exact, rel=1e-13)
+
+
+@pytest.mark.parametrize("cells", [(2, 2, 1), (3, 5, 1)])
+def test_wave_energy_closed_form(cells):
+    # u = v = x(1-x) y(1-y) lies in Q2 and vanishes on the boundary of the unit square, so the
+    # discrete energy (v^T M v + u^T A u) / 2 is the exact (int v^2 + int |grad u|^2) / 2
+    # = (1/900 + 1/45) / 2 = 21/1800 (coefficient 1)
+    cfg = Config(dim=2, problem=1, time_method=1, p=2, k=2, n_time_cells=1, n_cells=cells, tau=0.1)
+    verts, coef = draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    X = spatial.node_coordinates(op.space)
+    u = X[:, 0] * (1 - X[:, 0]) * X[:, 1] * (1 - X[:, 1])
+    assert norms.wave_energy(op, u, u) == pytest.approx(21.0 / 1800.0, rel=1e-12)
+    assert norms.wave_energy(op, u, np.zeros_like(u)) == pytest.approx(1.0 / 90.0, rel=1e-12)
