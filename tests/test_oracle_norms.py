@@ -1,6 +1,7 @@
-"""Pins of the oracle's L2(L2) error (eq. norms): the discrete solution that interpolates a
-space-time polynomial of the discrete degrees has zero error, and the error of the zero solution
-is the closed-form norm of the exact function."""
+"""Pins of the oracle's norms and loads: the L2(L2) error of eq. norms (zero for the interpolant
+of a space-time polynomial of the discrete degrees, the closed-form norm for the zero solution),
+the discrete wave energy of an exactly represented field, and the spatial load vectors of the
+slab right-hand sides (partition of unity; mass matrix times nodal values for f in Q_p)."""
 import numpy as np
 import pytest
 
@@ -54,3 +55,34 @@ def test_wave_energy_closed_form(cells):
     u = X[:, 0] * (1 - X[:, 0]) * X[:, 1] * (1 - X[:, 1])
     assert norms.wave_energy(op, u, u) == pytest.approx(21.0 / 1800.0, rel=1e-12)
     assert norms.wave_energy(op, u, np.zeros_like(u)) == pytest.approx(1.0 / 90.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("dim,p,perturb", [(2, 1, 0.15), (2, 3, 0.1), (3, 2, 0.1)])
+def test_loads_partition_of_unity(dim, p, perturb):
+    # the nodal basis sums to one and the boundary of the box is not perturbed, so the loads of
+    # f = 1 + x0 x1 sum to its integral over the unit box, 1 + 1/4, at every time (the Gauss rule
+    # is exact for this integrand on bilinear or trilinear cells)
+    from oracle import rhs
+    cells = (3, 2, 2) if dim == 3 else (3, 4, 1)
+    cfg = Config(dim=dim, problem=0, time_method=0, p=p, k=0, n_time_cells=1, n_cells=cells, tau=0.1,
+                 perturb=perturb, seed=8)
+    verts, coef = draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    f = lambda x, t: (1.0 + x[..., 0] * x[..., 1]) * (1.0 + t)
+    F = rhs.loads(op.space, f, np.array([0.0, 2.0]))
+    assert F.sum(axis=1) == pytest.approx([1.25, 3.75], rel=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_loads_of_a_discrete_field_are_mass_times_nodal_values(p):
+    # for f in Q_p the load vector is the assembled mass matrix applied to f's nodal values
+    from oracle import rhs
+    cfg = Config(dim=2, problem=0, time_method=0, p=p, k=0, n_time_cells=1, n_cells=(3, 2, 1), tau=0.1)
+    verts, coef = draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    f = lambda x, t: (2.0 - x[..., 0] ** p) * (1.0 + 3.0 * x[..., 1] ** p)
+    X = spatial.node_coordinates(op.space)
+    M, _ = spatial.assemble(op.space)
+    F = rhs.loads(op.space, f, np.array([0.0]))[0]
+    ref = M @ f(X, 0.0)
+    assert np.allclose(F, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
