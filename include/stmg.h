@@ -16,8 +16,9 @@
  *     (N_T = A_T for heat, A_T M_T^{-1} A_T for the condensed wave system);
  *   - solver: flexible GMRES in FP64, preconditioned by one space-time multigrid
  *     V-cycle per iteration (Section 3, Alg. stmg) with the space-time cell-wise
- *     additive Schwarz smoother (eqs. vanka0 and vanka) and spatial h/p transfers
- *     (Section 3.2, Alg. mg-sequence, spatial levels only).
+ *     additive Schwarz smoother (eqs. vanka0 and vanka), spatial h/p transfers
+ *     and, optionally, k- and tau-levels in time below the spatial ones
+ *     (Section 3.2, Alg. mg-sequence).
  *
  * Vector layout (every device vector argument): time-major [n_t][N_x], where
  * N_x = prod_d (p * n_cells[d] + 1) lattice nodes ordered x fastest, n_t =
@@ -32,6 +33,10 @@
  * Streams: every call enqueues its kernels on the hipStream_t given at
  * creation.  stmg_vmult, stmg_smooth, stmg_vcycle, stmg_prolongate and
  * stmg_restrict are asynchronous.  stmg_create and stmg_solve synchronise.
+ *
+ * Host-only queries (stmg_temporal_matrices, stmg_temporal_cell_factors,
+ * stmg_temporal_prolongation, stmg_transfer_1d) need no handle and no device;
+ * they fill caller-owned host arrays with the set-up data the library builds.
  *
  * Errors: every function returns an stmg_status; nothing is thrown or aborted
  * across the ABI.  stmg_last_error() returns a thread-local message for the
