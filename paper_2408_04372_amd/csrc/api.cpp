@@ -265,6 +265,7 @@ stmg_status stmg_cnn_create(stmg_handle* h, int n_layers, const int32_t* channel
   return guarded([&]() -> stmg_status {
     level_of(h, 0);
     if (!channels) stmg::fail(STMG_E_ARG, "channels is NULL");
+    if (n_layers < 1 || n_layers > 6) stmg::fail(STMG_E_ARG, "n_layers must be in 1..6");
     std::vector<int> ch(channels, channels + n_layers + 1);
     stmg::cnn_create(h, n_layers, ch.data());
     h->krylov_m = 0;
