@@ -151,3 +151,97 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------- rounding scales
+# Per-element scales of the rounding error of a low-precision evaluation of the same network
+# (weights, activations and upstream gradients rounded to a format of unit roundoff u, products
+# and sums in a wider format), for element-by-element comparisons.  Rounding errors of different
+# terms are independent to first order, so the error of a sum has the scale u times the square
+# root of the summed variances of its terms: a term w h contributes w^2 var(h) (error carried in
+# h) plus (w h)^2 (rounding of w); each rounded result adds its own square.  Variances propagate
+# through the layers like the values do (squared weights acting on variances).  The functions
+# return sigma / u.
+
+def _forward_vars(theta, channels, r, bmask):
+    z, (s, hs) = forward(theta, channels, r, bmask, keep=True)
+    layers = unpack(theta, channels)
+    var = [hs[0] ** 2]                                  # rounding of the normalised input
+    for l, (W, b) in enumerate(layers):
+        zero = np.zeros_like(b)
+        v = conv(var[-1], W ** 2, zero) + conv(hs[l] ** 2, W ** 2, zero)
+        if l < len(layers) - 1:
+            v = v * (hs[l + 1] > 0) + hs[l + 1] ** 2      # relu, then rounding of the activation
+        var.append(v)
+    return s, hs, var, layers
+
+
+def forward_rounding_scale(theta, channels, r, bmask=None):
+    """sigma(v) / u for every output element of C(r)."""
+    s, hs, var, layers = _forward_vars(theta, channels, r, bmask)
+    out = s * np.sqrt(var[-1])
+    if bmask is not None:
+        out[:, bmask] = 0.0
+    return out
+
+
+def output_gradient_rounding_scale(theta, channels, r, dz, bmask=None):
+    """sigma / u for every entry of output_gradient (weight gradients sum g h over the lattice,
+    bias gradients sum g)."""
+    s, hs, hvar, layers = _forward_vars(theta, channels, r, bmask)
+    g = dz.copy()
+    if bmask is not None:
+        g[:, bmask] = 0.0
+    g = g * s
+    gvar = g ** 2                                       # rounding of the upstream gradient
+    out = []
+    for l in range(len(layers) - 1, -1, -1):
+        W, b = layers[l]
+        dW_a, _, _ = conv_backward(hvar[l], W, g ** 2)   # error carried in h
+        dW_b, db_v, _ = conv_backward(hs[l] ** 2, W, gvar)   # error carried in g
+        out.append((np.sqrt(dW_a + dW_b), np.sqrt(db_v)))
+        if l > 0:
+            _, _, dh = conv_backward(hs[l], W, g)
+            _, _, dv1 = conv_backward(hs[l], W ** 2, gvar)
+            _, _, dv2 = conv_backward(hs[l], W ** 2, g ** 2)
+            mask = hs[l] > 0
+            g = dh * mask
+            gvar = (dv1 + dv2) * mask + g ** 2
+    out = out[::-1]
+    return np.concatenate([np.concatenate([a.ravel(), c]) for a, c in out])
+
+
+def output_gradient_flip_bound(theta, channels, r, dz, bmask=None, u=2.0 ** -9, k=8.0):
+    """Bound on the change of every entry of output_gradient when the relu decisions differ at
+    the pre-activations that lie within k rounding scales (k u sigma) of zero: a low-precision
+    evaluation may take either branch there.  A flipped decision at node v changes the upstream
+    gradient there by at most |dh(v)|; that change reaches the weight and bias gradients of the
+    layer below and, through |W|, the layers further down (absolute sums: flips are few and
+    need not be independent)."""
+    z, (s, hs) = forward(theta, channels, r, bmask, keep=True)
+    _, _, hvar, layers = _forward_vars(theta, channels, r, bmask)
+    # pre-activations of the hidden layers and their rounding scales
+    pre = []
+    for l, (W, b) in enumerate(layers[:-1]):
+        a = conv(hs[l], W, b)
+        sig = np.sqrt(conv(hvar[l], W ** 2, np.zeros_like(b)) + conv(hs[l] ** 2, W ** 2, np.zeros_like(b)))
+        pre.append(np.abs(a) <= k * u * sig)
+    g = dz.copy()
+    if bmask is not None:
+        g[:, bmask] = 0.0
+    g = g * s
+    E = np.zeros_like(g)                      # bound on the change of g at this layer
+    out = []
+    for l in range(len(layers) - 1, -1, -1):
+        W, b = layers[l]
+        dWe, dbe, _ = conv_backward(np.abs(hs[l]), W, E)
+        out.append((dWe, dbe))
+        if l > 0:
+            _, _, dh = conv_backward(hs[l], W, g)
+            _, _, dhE = conv_backward(hs[l], np.abs(W), E)
+            amb = pre[l - 1]
+            mask = hs[l] > 0
+            g = dh * mask
+            E = dhE * (mask | amb) + np.abs(dh) * amb
+    out = out[::-1]
+    return np.concatenate([np.concatenate([a.ravel(), c]) for a, c in out])
