@@ -136,3 +136,59 @@ def test_bitwise_reproducible(name):
     assert outs[0][0] == outs[1][0]
     for a, b in zip(outs[0][1:], outs[1][1:]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("where", ["rhs", "initial_guess"])
+def test_nonfinite_input_rejected(where):
+    # a NaN in b (or an Inf in x0) is found by the norm check before the first iteration:
+    # STMG_E_NONFINITE, and the handle stays usable
+    from paper_2408_04372_amd import StmgError
+    from tests.gpu_common import problem
+    cfg, verts, coef = problem("heat3d_q2_dg1_pert")
+    print(f"case nonfinite {where}", flush=True)
+    h = _handle(cfg, verts, coef, omega=-1.0, rtol=1e-10, precision=0)
+    try:
+        b = si.random_slab_vector(cfg, 91)
+        bt = _t(b)
+        x = torch.zeros_like(bt)
+        interior = int(np.flatnonzero(b[1])[3]) + h.info["n_x"][0]
+        if where == "rhs":
+            bt[interior] = float("nan")
+        else:
+            x[interior] = float("inf")
+        with pytest.raises(StmgError) as e:
+            h.solve(bt, x)
+        assert e.value.code == 5
+        assert "NaN" in h.lib.stmg_last_error().decode()
+        bt = _t(b)
+        x.zero_()
+        info = h.solve(bt, x)
+        assert info["status"] == "OK" and info["rel_residual"] <= 1e-10
+    finally:
+        h.close()
+
+
+def test_max_iter_reports_noconv_with_info():
+    # max_iter = 1: STMG_E_NOCONV with info filled (one iteration, the true relative residual
+    # of the returned x, timing buckets)
+    from tests.gpu_common import problem
+    cfg, verts, coef = problem("heat3d_q2_dg1_pert")
+    print("case max_iter 1", flush=True)
+    h = _handle(cfg, verts, coef, omega=-1.0, rtol=1e-14, precision=0, max_iter=1)
+    try:
+        b = si.random_slab_vector(cfg, 92)
+        bt = _t(b)
+        x = torch.zeros_like(bt)
+        info = h.solve(bt, x, raise_on_noconv=False)
+        assert info["status"] == "E_NOCONV"
+        assert "max_iter" in h.lib.stmg_last_error().decode()
+        assert info["iterations"] == 1
+        Sx = torch.empty_like(x)
+        h.vmult(x, Sx)
+        true_rel = (torch.linalg.norm(bt - Sx) / torch.linalg.norm(bt)).item()
+        print("noconv info", info, "true rel", true_rel, flush=True)
+        assert 0.0 < info["rel_residual"] < 1.0
+        assert abs(info["rel_residual"] - true_rel) <= 1e-12 + 1e-10 * true_rel
+        assert info["seconds"] > 0.0 and info["t_gmg_other"] + info["t_smoother"] > 0.0
+    finally:
+        h.close()

@@ -1,8 +1,9 @@
 """GPU parity: the C-ABI library against the FP64 CPU oracle on the same seeded inputs.
 
-Tolerances: FP64 kernels accumulate with hardware atomics (summation order is not
-fixed), so results agree to a few ulps of the largest entry: 1e-12 relative to the
-max norm.  FP32 kernels: 2e-5 (a few FP32 ulps times the sum-factorisation depth).
+Tolerances: the FP64 kernels sum in a fixed order that differs from the oracle's
+(sum factorisation instead of assembled sparse rows, per-cell contributions gathered
+node by node), so results agree to a few ulps of the largest entry: 1e-12 relative to
+the max norm.  FP32 kernels: 2e-5 (a few FP32 ulps times the sum-factorisation depth).
 Solutions: 1e-10 relative (FP64 path), true residual 1e-8 (FP32-preconditioned path).
 """
 import numpy as np
