@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define STMG_ABI_VERSION 3
+#define STMG_ABI_VERSION 4
 
 typedef enum {
   STMG_OK = 0,
@@ -69,6 +69,16 @@ typedef enum { STMG_HEAT = 0, STMG_WAVE = 1 } stmg_problem;
 typedef enum { STMG_DG = 0, STMG_CGP = 1 } stmg_time_method;
 typedef enum { STMG_F64 = 0, STMG_F32 = 1 } stmg_dtype;
 typedef enum { STMG_PREC_FP64 = 0, STMG_PREC_FP32 = 1, STMG_PREC_LEARNED = 2 } stmg_precision;
+/* How the operator (eq. lin-sys) and the smoother (eq. vanka0) sum the contributions of cells
+ * that share lattice nodes; all three give the same result up to rounding order, and each is
+ * bitwise reproducible.
+ * DEFAULT: on 3D levels with axis-aligned cells and one coefficient per cell the operator runs on
+ *   bricks of cells summed in LDS, launched in 2^3 brick colours (face nodes updated in colour
+ *   order); other levels as PER_CELL.
+ * PER_CELL: every cell writes its contribution to a per-cell buffer and a node gather sums them in
+ *   a fixed cell order (a level whose buffer cannot be allocated falls back to COLOUR).
+ * COLOUR: 2^d colour launches of cells that share no node, each adding into the vector. */
+typedef enum { STMG_PATH_DEFAULT = 0, STMG_PATH_PER_CELL = 1, STMG_PATH_COLOUR = 2 } stmg_kernel_path;
 
 /* One slab problem and its solver settings.  Fields follow the paper's notation. */
 typedef struct {
@@ -105,6 +115,7 @@ typedef struct {
                               cGP 1), then merge pairs of time cells while their number is even;
                               temporal prolongation = embedding of the coarse trial functions,
                               restriction its transpose; needs n_t <= 32 */
+  int32_t kernel_path;     /* stmg_kernel_path: how operator and smoother sum the cell contributions */
 } stmg_config;
 
 typedef struct {

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstmg.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_LEVELS = 16
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 5: "E_NONFINITE",
@@ -39,7 +39,7 @@ class CConfig(ctypes.Structure):
         ("vcycle_dtypes", ctypes.c_int32), ("omega", ctypes.c_double),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("gram_schmidt", ctypes.c_int32), ("rtol", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("asm_variant", ctypes.c_int32), ("time_mg", ctypes.c_int32),
+        ("asm_variant", ctypes.c_int32), ("time_mg", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
     ]
 
 
@@ -223,6 +223,7 @@ def c_config(cfg, **overrides) -> CConfig:
     c.gram_schmidt = int(overrides.get("gram_schmidt", 0))
     c.asm_variant = int(overrides.get("asm_variant", getattr(cfg, "asm_variant", 0)))
     c.time_mg = int(overrides.get("time_mg", 0))
+    c.kernel_path = int(overrides.get("kernel_path", 0))
     c.omega = float(get("omega"))
     c.rtol = float(get("rtol"))
     c.seed = int(get("seed"))

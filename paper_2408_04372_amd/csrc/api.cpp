@@ -57,6 +57,8 @@ void check_config(const stmg_config* c) {
   if (c->gram_schmidt != 0 && c->gram_schmidt != 1) fail(STMG_E_ARG, "gram_schmidt must be 0 or 1");
   if (c->asm_variant != 0 && c->asm_variant != 1) fail(STMG_E_ARG, "asm_variant must be 0 or 1");
   if (c->time_mg != 0 && c->time_mg != 1) fail(STMG_E_ARG, "time_mg must be 0 or 1");
+  if (c->kernel_path < STMG_PATH_DEFAULT || c->kernel_path > STMG_PATH_COLOUR)
+    fail(STMG_E_ARG, "kernel_path must be 0, 1 or 2");
   if (c->max_iter < 1) fail(STMG_E_ARG, "max_iter must be >= 1");
   if (!(c->rtol > 0.0)) fail(STMG_E_ARG, "rtol must be positive");
   if (c->vcycle_dtypes < 0 || c->vcycle_dtypes > 3) fail(STMG_E_ARG, "vcycle_dtypes must be in 0..3");

@@ -1,0 +1,221 @@
+// Brick tiling shared by the brick operator and the brick smoother (Cartesian 3D levels).
+//
+// A workgroup owns a brick of B_x x B_y x B_z cells.  The brick's lattice nodes, (p B + 1) per
+// direction and every temporal plane, are staged once in LDS; the cells' results are summed into
+// that LDS copy in eight rounds, one per cell parity class (cells of one class share no node), and
+// every node of the brick is then written to HBM once.  Bricks are launched in 2^3 parity colours:
+// bricks of one colour share no node, and a node on a brick face is stored by the brick of the
+// lowest colour holding it (with the base vector, in overwrite mode) and updated by the others in
+// colour order.  The summation order is fixed, so results are bitwise reproducible, without atomics.
+#pragma once
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace stmg {
+
+// launch description of one brick colour
+struct BrickLaunch {
+  int B[3];           // brick size in cells
+  int NBd[3];         // brick lattice nodes per direction (p B + 1)
+  int nbt[3];         // bricks per direction (all colours)
+  int nbc[3];         // bricks of this colour per direction
+  int colour;
+  int nblocks;
+};
+
+// this workgroup's brick
+struct BrickPos {
+  int b[3];           // brick coordinates
+  int c0[3];          // first cell
+  int nc[3];          // cells of the brick inside the mesh (the last brick per direction may be short)
+  int g0[3];          // first lattice node
+  int NB;             // nodes per temporal plane of the (full-size) brick box
+};
+
+__device__ inline BrickPos brick_pos(const BrickLaunch& L, const GeomDesc& g) {
+  BrickPos P;
+  const int lb = xcd_swizzle(blockIdx.x, L.nblocks);
+  const int ib[3] = {lb % L.nbc[0], (lb / L.nbc[0]) % L.nbc[1], lb / (L.nbc[0] * L.nbc[1])};
+  for (int d = 0; d < 3; ++d) {
+    P.b[d] = 2 * ib[d] + ((L.colour >> d) & 1);
+    P.c0[d] = P.b[d] * L.B[d];
+    P.nc[d] = min(L.B[d], g.nc[d] - P.c0[d]);
+    P.g0[d] = P.c0[d] * g.p;
+  }
+  P.NB = L.NBd[0] * L.NBd[1] * L.NBd[2];
+  return P;
+}
+
+// Rows (plane j, z, y) of the brick's node box: thread `tid` keeps its x position and walks the
+// rows r0, r0 + per, r0 + 2 per, ... with a carried (j, z, y) counter (no integer division in the
+// loop).  Rows come in batches so that every global load of a batch is issued before the first of
+// them is used.
+struct RowWalk {
+  int per, lx, ly, lz, j;
+  bool on;
+  __device__ RowWalk(int tid, int nthr, const int NBd[3]) {
+    per = nthr / NBd[0];
+    lx = tid % NBd[0];
+    const int r0 = tid / NBd[0];
+    on = r0 < per;
+    ly = r0 % NBd[1];
+    lz = (r0 / NBd[1]) % NBd[2];
+    j = r0 / (NBd[1] * NBd[2]);
+  }
+  __device__ void next(const int NBd[3]) {
+    ly += per;
+    while (ly >= NBd[1]) {
+      ly -= NBd[1];
+      if (++lz == NBd[2]) { lz = 0; ++j; }
+    }
+  }
+};
+constexpr int ROW_BATCH = 16;
+
+// Order LDS accesses of one wave: the LDS executes a wave's operations in issue order, so a value
+// written by one lane is visible to another lane of the same wave once the compiler keeps the
+// write before the read (a team never straddles two waves).
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// xs[j][node] = x on the brick's nodes for every temporal plane j < n_t (Dirichlet nodes and nodes
+// past the lattice read as zero).
+template <class T>
+__device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                   const T* __restrict__ x, T* xs) {
+  const int nbx = L.NBd[0], nby = L.NBd[1];
+  const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
+  RowWalk w(threadIdx.x, blockDim.x, L.NBd);
+  while (w.on && w.j < n_t) {
+    T v[ROW_BATCH];
+    int dst[ROW_BATCH];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) {
+      v[u] = 0;
+      dst[u] = -1;
+      if (w.j < n_t) {
+        const int gx = P.g0[0] + w.lx, gy = P.g0[1] + w.ly, gz = P.g0[2] + w.lz;
+        const bool in = gx > 0 && gx < nn0 - 1 && gy > 0 && gy < nn1 - 1 && gz > 0 && gz < nn2 - 1;
+        if (in) v[u] = x[(long long)w.j * g.nx + ((long long)gz * nn1 + gy) * nn0 + gx];
+        dst[u] = w.j * P.NB + (w.lz * nby + w.ly) * nbx + w.lx;
+        w.next(L.NBd);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u)
+      if (dst[u] >= 0) xs[dst[u]] = v[u];
+  }
+}
+
+// Write the brick's sums xs (n_t planes) to y:
+//   overwrite: y = base + scale * xs by the brick of the lowest colour holding the node (base null:
+//              zero), y += scale * xs by the others; Dirichlet nodes receive base (or zero) only;
+//   otherwise: y += scale * xs on interior nodes.
+template <class T>
+__device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                   const T* xs, T scale, int overwrite, const T* __restrict__ base, T* y) {
+  const int nbx = L.NBd[0], nby = L.NBd[1];
+  const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
+  const int p = g.p;
+  const int last[3] = {P.nc[0] * p, P.nc[1] * p, P.nc[2] * p};
+  RowWalk w(threadIdx.x, blockDim.x, L.NBd);
+  while (w.on && w.j < n_t) {
+    long long gi[ROW_BATCH];
+    int mode[ROW_BATCH];        // -1 skip, 0 boundary store, 1 store (base + v), 2 update
+    T old[ROW_BATCH], v[ROW_BATCH];
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u) {
+      mode[u] = -1;
+      old[u] = 0;
+      v[u] = 0;
+      gi[u] = 0;
+      if (w.j < n_t) {
+        const int lx = w.lx, ly = w.ly, lz = w.lz;
+        if (lx <= last[0] && ly <= last[1] && lz <= last[2]) {      // inside the brick's cells
+          const int gx = P.g0[0] + lx, gy = P.g0[1] + ly, gz = P.g0[2] + lz;
+          const bool shx = (lx == 0 && P.b[0] > 0) || (lx == last[0] && P.b[0] + 1 < L.nbt[0]);
+          const bool shy = (ly == 0 && P.b[1] > 0) || (ly == last[1] && P.b[1] + 1 < L.nbt[1]);
+          const bool shz = (lz == 0 && P.b[2] > 0) || (lz == last[2] && P.b[2] + 1 < L.nbt[2]);
+          const bool first = !(shx && (P.b[0] & 1)) && !(shy && (P.b[1] & 1)) && !(shz && (P.b[2] & 1));
+          const bool bnd = gx == 0 || gx == nn0 - 1 || gy == 0 || gy == nn1 - 1 || gz == 0 || gz == nn2 - 1;
+          gi[u] = (long long)w.j * g.nx + ((long long)gz * nn1 + gy) * nn0 + gx;
+          const bool store = overwrite && first;
+          mode[u] = bnd ? (store ? 0 : -1) : (store ? 1 : 2);
+          if (mode[u] == 0 || mode[u] == 1) old[u] = base ? base[gi[u]] : (T)0;
+          else if (mode[u] == 2) old[u] = y[gi[u]];
+          if (mode[u] >= 1) v[u] = scale * xs[w.j * P.NB + (lz * nby + ly) * nbx + lx];
+        }
+        w.next(L.NBd);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < ROW_BATCH; ++u)
+      if (mode[u] >= 0) y[gi[u]] = old[u] + v[u];
+  }
+}
+
+struct BrickPlan {
+  int B[3] = {1, 1, 1};
+  int waves = 1;
+  size_t lds = 0;
+};
+
+// Brick size: the largest product of the share of owned nodes, lane use and LDS occupancy (eight
+// waves per CU count as full), with at most 8 waves, every work item of the brick (items_per_cell
+// per cell, one team of team_lanes lanes each, teams never straddling a wave) in one round of teams, and LDS (n_t planes of the box,
+// team_scratch values per team, plus `extra` bytes) within budget.
+inline bool plan_brick(const GeomDesc& g, int n_t, int items_per_cell, int team_lanes, size_t elem,
+                       int team_scratch, size_t extra, BrickPlan& out) {
+  const int p = g.p;
+  const int tpw = 64 / team_lanes;
+  static const int cand[][3] = {{4, 3, 2}, {4, 2, 2}, {3, 3, 2}, {3, 2, 2}, {2, 2, 2}, {3, 2, 1},
+                                {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+  double best = -1.0;
+  for (auto& c : cand) {
+    int B[3] = {std::min(c[0], g.nc[0]), std::min(c[1], g.nc[1]), std::min(c[2], g.nc[2])};
+    const long long items = (long long)B[0] * B[1] * B[2] * items_per_cell;
+    const int waves = (int)((items + tpw - 1) / tpw);
+    if (waves > 8) continue;
+    const long long nb = (long long)(p * B[0] + 1) * (p * B[1] + 1) * (p * B[2] + 1);
+    const size_t lds = elem * ((size_t)n_t * nb + (size_t)waves * tpw * team_scratch) + extra;
+    if (lds > 72 * 1024) continue;
+    const double owned = (double)(p * B[0]) * (p * B[1]) * (p * B[2]) / (double)nb;
+    const double use = (double)items / ((double)waves * tpw);
+    const double occ = std::min(1.0, (double)((160 * 1024) / lds) * waves / 8.0);
+    const double score = owned * use * occ;
+    if (score > best + 1e-9) {
+      best = score;
+      out.B[0] = B[0]; out.B[1] = B[1]; out.B[2] = B[2];
+      out.waves = waves;
+      out.lds = lds;
+    }
+  }
+  return best > 0.0;
+}
+
+// per-colour launch descriptions; a colour without bricks has nblocks = 0
+inline void brick_launches(const GeomDesc& g, const BrickPlan& pl, BrickLaunch out[8]) {
+  for (int colour = 0; colour < 8; ++colour) {
+    BrickLaunch& L = out[colour];
+    long long cnt = 1;
+    for (int d = 0; d < 3; ++d) {
+      L.B[d] = pl.B[d];
+      L.NBd[d] = g.p * pl.B[d] + 1;
+      L.nbt[d] = (g.nc[d] + pl.B[d] - 1) / pl.B[d];
+      const int o = (colour >> d) & 1;
+      L.nbc[d] = (L.nbt[d] - o + 1) / 2;
+      cnt *= L.nbc[d];
+    }
+    if (cnt > (1LL << 31) - 1) fail(STMG_E_UNSUPPORTED, "too many bricks");
+    L.colour = colour;
+    L.nblocks = (int)cnt;
+  }
+}
+
+}  // namespace stmg

@@ -49,6 +49,8 @@ struct Level {
   int ratio = 1;              // finest cells per cell of this level, per direction
   GeomDesc g;
   LevelTables lt;
+  CartTables ct;              // separable cell matrices (brick operator)
+  bool brick = false;         // the operator runs on the brick kernel (3D Cartesian, rho per cell)
   DevBuf verts, rho, bidx, mask;
   long long nb = 0;           // boundary nodes per temporal plane
   long long n_int = 0;        // interior nodes per temporal plane

@@ -531,7 +531,7 @@ void setup_smoother(stmg_handle* h, Level& L) {
 }
 
 template <class T>
-void alloc_work(Level& L, int n_t, bool coarsest) {
+void alloc_work(Level& L, int n_t, bool coarsest, bool colour_only) {
   LevelData<T>& d = ldata<T>(L);
   size_t n = (size_t)L.g.nx * n_t * sizeof(T);
   d.u.alloc(n);
@@ -540,10 +540,12 @@ void alloc_work(Level& L, int n_t, bool coarsest) {
   {
     const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
     const size_t bytes = sizeof(T) * L.g.ncells * n_t * nq;
-    // small levels need the buffer; on large levels it only speeds up the apply, and without
-    // it (device memory exhausted) the level runs on the colour path
-    if (L.g.ncells <= TWO_PHASE_MAX_CELLS) d.cellbuf.alloc(bytes);
-    else (void)d.cellbuf.try_alloc(bytes);
+    // the buffer only speeds up the apply: without it (device memory exhausted on a large level,
+    // or the colour path requested) the level runs on 2^d colour launches
+    if (!colour_only) {
+      if (L.g.ncells <= TWO_PHASE_MAX_CELLS) d.cellbuf.alloc(bytes);
+      else (void)d.cellbuf.try_alloc(bytes);
+    }
   }
   if (!coarsest) {
     d.tmpA.alloc(n);
@@ -682,6 +684,8 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
       L->g.verts = L->verts.as<double>();
     }
     level_coefficients(*L, coef, fine_cells, s);
+    L->ct = make_cart_tables(L->lt);
+    L->brick = cfg.kernel_path == STMG_PATH_DEFAULT && brick_applicable(L->g);
     if (cfg.asm_variant == 1) {
       // cell mean of the finest coefficient over the ratio^d finest cells of each cell
       const int r = L->ratio;
@@ -725,10 +729,11 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
   for (size_t l = 0; l < h->levels.size(); ++l) {
     Level& L = *h->levels[l];
     bool coarsest = (l + 1 == h->levels.size());
-    if (L.has64) alloc_work<double>(L, L.n_t(), coarsest);
-    if (L.has32) alloc_work<float>(L, L.n_t(), coarsest);
+    const bool colour_only = cfg.kernel_path == STMG_PATH_COLOUR;
+    if (L.has64) alloc_work<double>(L, L.n_t(), coarsest, colour_only);
+    if (L.has32) alloc_work<float>(L, L.n_t(), coarsest, colour_only);
     // the outer FP64 operator of the solver runs on the finest level in every mode
-    if (l == 0 && !L.has64) {
+    if (l == 0 && !L.has64 && !L.brick && !colour_only) {
       const long long nq = L.g.dim == 3 ? (long long)L.g.n * L.g.n * L.g.n : (long long)L.g.n * L.g.n;
       const size_t bytes = sizeof(double) * L.g.ncells * L.n_t() * nq;
       if (L.g.ncells <= TWO_PHASE_MAX_CELLS) L.d64.cellbuf.alloc(bytes);
@@ -754,9 +759,11 @@ template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y) {
   hipStream_t s = h->stream;
   long long n = L.nst(L.n_t());
   T* cb = ldata<T>(L).cellbuf.template as<T>();
-  if (!cb) fill<T>(y, (T)0, n, s);      // the per-cell buffer path writes y itself
+  // the brick and per-cell buffer paths write y themselves
+  if (!cb && !L.brick) fill<T>(y, (T)0, n, s);
   if (level == 0) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(L), x, y, (T)1, s, cb, nullptr, cb != nullptr);
+  if (L.brick) st_apply_brick<T>(L.g, L.ct, tdev<T>(L), x, y, (T)1, s, nullptr, true);
+  else st_apply<T>(L.g, L.lt, tdev<T>(L), x, y, (T)1, s, cb, nullptr, cb != nullptr);
   if (level == 0) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)1, x, (T)0, y, s);
 }
@@ -766,10 +773,12 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
   hipStream_t s = h->stream;
   long long n = L.nst(L.n_t());
   T* cb = ldata<T>(L).cellbuf.template as<T>();
-  if (!cb) copy<T>(f, r, n, s);         // the per-cell buffer path reads f in its gather
+  // the brick and per-cell buffer paths read f themselves
+  if (!cb && !L.brick) copy<T>(f, r, n, s);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(0, s);
-  st_apply<T>(L.g, L.lt, tdev<T>(L), u, r, (T)-1, s, cb, f, cb != nullptr);
+  if (L.brick) st_apply_brick<T>(L.g, L.ct, tdev<T>(L), u, r, (T)-1, s, f, true);
+  else st_apply<T>(L.g, L.lt, tdev<T>(L), u, r, (T)-1, s, cb, f, cb != nullptr);
   if (fine) h->ktimer.end(s);
   boundary_axpby<T>(L.bidx.as<int>(), L.nb, L.g.nx, L.n_t(), (T)-1, u, (T)1, r, s);
 }
@@ -778,12 +787,18 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
 template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u, bool u_zero = false) {
   LevelData<T>& d = ldata<T>(L);
   T* cb = d.cellbuf.template as<T>();
-  if (u_zero && !cb) fill<T>(u, (T)0, L.nst(L.n_t()), h->stream);
+  const bool u_zero_in = u_zero;       // the brick smoother writes u itself
+  const bool brick_fdm = h->cfg.asm_variant == 1 && L.brick && fdm_brick_applicable(L.g, L.ts->tm.nt_cell);
+  if (u_zero && !cb && !brick_fdm) fill<T>(u, (T)0, L.nst(L.n_t()), h->stream);
   u_zero = u_zero && cb;
   h->timer.mark(TB_SMOOTH, h->stream);
   bool fine = (&L == h->levels[0].get());
   if (fine) h->ktimer.begin(1, h->stream);
-  if (h->cfg.asm_variant == 1)
+  if (brick_fdm)
+    asm_apply_fdm_brick<T>(L.g, L.n_t(), L.ts->tm.nt_cell, L.ts->tm.M_tau.a.data(), L.ts->tm.N_tilde.a.data(),
+                           d.fq.template as<T>(), d.fl.template as<T>(), d.frho.template as<T>(), r, u,
+                           (T)L.omega, u_zero_in, h->stream);
+  else if (h->cfg.asm_variant == 1)
     asm_apply_fdm<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
                      d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream, cb,
                      u_zero);

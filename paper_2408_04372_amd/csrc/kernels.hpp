@@ -35,6 +35,23 @@ constexpr long long TWO_PHASE_MAX_CELLS = 4096;
 template <class T> void cell_gather(const GeomDesc& g, int n_t, const T* cb, T* y, hipStream_t s,
                                     const T* base = nullptr, bool overwrite = false);
 
+// ---- brick operator (op_brick.hip) -----------------------------------------------------------
+// 1D reference mass and stiffness of Q_p on [0, 1] (GLL nodal basis, exact Gauss quadrature),
+// row-major n x n.  Host only.
+struct CartTables {
+  int n = 0;
+  std::vector<double> M, K;
+};
+CartTables make_cart_tables(const LevelTables& lt);
+// 3D level with axis-aligned box cells and one coefficient per cell
+bool brick_applicable(const GeomDesc& g);
+// y = base + scale * S_interior x on interior rows (overwrite; base null: zero; Dirichlet rows of y
+// receive base or zero) or y += scale * S_interior x; bricks of cells staged in LDS, 2^3 brick
+// colours, no per-cell buffer.
+template <class T>
+void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T>& tp, const T* x, T* y,
+                    T scale, hipStream_t s, const T* base, bool overwrite);
+
 // ---- vector kernels (blas.hip) --------------------------------------------------------------
 template <class T> void fill(T* y, T v, long long n, hipStream_t s);
 template <class T> void copy(const T* x, T* y, long long n, hipStream_t s);
@@ -111,6 +128,15 @@ template <class T>
 void asm_apply_fdm(const GeomDesc& g, int n_t, int nt_cell, const T* fq, const T* fl, const T* frho,
                    const T* ftm, const T* r, T* u, T omega, hipStream_t s, T* cellbuf = nullptr,
                    bool u_zero = false);
+
+// Brick-tiled separable smoother (asm_brick.hip) on 3D Cartesian levels with one or two temporal
+// DoFs per time cell: same result as asm_apply_fdm; Mtau, Ntil are the host (nt_cell x nt_cell,
+// row-major) time-cell matrices; u_zero: u is zero on entry and not read.
+bool fdm_brick_applicable(const GeomDesc& g, int nt_cell);
+template <class T>
+void asm_apply_fdm_brick(const GeomDesc& g, int n_t, int nt_cell, const double* Mtau, const double* Ntil,
+                         const T* fq, const T* fl, const T* frho, const T* r, T* u, T omega, bool u_zero,
+                         hipStream_t s);
 
 // ---- smoother set-up check (hierarchy.hip) ----------------------------------------------------
 // flag[c] = 1 unless cell c's eigenpairs pass: max|R - I| <= tol for R = Q^T M Q, and per column k

@@ -30,7 +30,22 @@ CASES = {
                                    n_cells=(3, 2, 2), tau=0.05, coef="lognormal", coef_sigma=1.0, seed=27),
     "heat3d_q2_dg1_c8_ragged": si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=8,
                                          n_cells=(3, 4, 2), tau=0.05, perturb=0.1, seed=28),
+    # Cartesian boxes with one coefficient per cell (brick operator): several bricks per direction
+    # with a ragged last brick, non-cubic cells
+    "heat3d_q4_dg1_brick": si.Config(dim=3, problem=0, time_method=0, p=4, k=1, n_time_cells=2,
+                                     n_cells=(5, 4, 3), tau=0.02, hi=(1.0, 0.8, 1.2), coef="lognormal",
+                                     coef_sigma=0.5, seed=29),
+    "heat3d_q2_dg1_c4_brick": si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=4,
+                                        n_cells=(9, 6, 5), tau=0.03, coef="lognormal", coef_sigma=1.0,
+                                        seed=30),
+    "wave3d_q3_cgp2_brick": si.Config(dim=3, problem=1, time_method=1, p=3, k=2, n_time_cells=2,
+                                      n_cells=(4, 5, 3), tau=0.02, hi=(1.0, 1.3, 0.9),
+                                      coef="lognormal_checker", coef_sigma=1.0, seed=31),
 }
+
+# Cartesian 3D cases whose operator runs on the brick kernel by default
+BRICK_CASES = ["heat3d_q4_dg1_brick", "heat3d_q2_dg1_c4_brick", "wave3d_q3_cgp2_brick", "heat3d_q1_dg0",
+               "wave3d_q3_cgp2_c4"]
 
 
 def problem(name):

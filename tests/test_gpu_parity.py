@@ -1,9 +1,9 @@
 """GPU parity: the C-ABI library against the FP64 CPU oracle on the same seeded inputs.
 
 Tolerances: the FP64 kernels sum in a fixed order that differs from the oracle's
-(sum factorisation instead of assembled sparse rows, per-cell contributions gathered
-node by node), so results agree to a few ulps of the largest entry: 1e-12 relative to
-the max norm.  FP32 kernels: 2e-5 (a few FP32 ulps times the sum-factorisation depth).
+(sum factorisation instead of assembled sparse rows, cell contributions summed node by
+node in a fixed cell order, or per brick and then in brick-colour order), so results agree
+to a few ulps of the largest entry: 1e-12 relative to the max norm.  FP32 kernels: 2e-5 (a few FP32 ulps times the sum-factorisation depth).
 Solutions: 1e-10 relative (FP64 path), true residual 1e-8 (FP32-preconditioned path).
 """
 import numpy as np
@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import stmg_inputs as si
 from oracle import krylov, mg, spacetime
-from tests.gpu_common import CASES, oracle_op, problem, rel_err
+from tests.gpu_common import BRICK_CASES, CASES, oracle_op, problem, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -280,3 +280,67 @@ def test_slab_rhs_matches_oracle(name):
         got_f = _np(b).reshape(ref.shape)
     assert rel_err(got, ref) < 1e-12
     assert rel_err(got_f, ref_f) < 1e-12
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("name", ["heat3d_q4_dg1_brick", "wave3d_q3_cgp2_brick", "heat3d_q2_dg1_c4_brick",
+                                  "heat3d_q2_dg1_pert", "heat2d_q2_dg1"])
+def test_kernel_paths(name, path):
+    """Operator, smoother (exact and separable blocks where the mesh allows) and V-cycle through each
+    way of summing cell contributions: bricks (0, Cartesian 3D levels), per-cell buffers (1) and
+    2^d colour launches (2), against the oracle."""
+    cfg, verts, coef = problem(name)
+    print(f"case {name} path {path}", flush=True)
+    op = oracle_op(cfg, verts, coef)
+    rng = np.random.default_rng(51)
+    x = rng.standard_normal((cfg.n_t, cfg.n_x))
+    ref = op.apply(x)
+    variants = [0] if verts is not None else [0, 1]
+    for av in variants:
+        H = mg.Hierarchy(op, n_smooth=cfg.n_smooth, asm_variant=av, omega_rule=-1.0)
+        lev = H.levels[-1]
+        b = rng.standard_normal(lev.S.shape[0])
+        x0 = rng.standard_normal(lev.S.shape[0])
+        omega = 0.37
+        sref = mg.smooth(lev, b, x0, 2, omega=omega)
+        r = rng.standard_normal(lev.S.shape[0])
+        vref = H.vcycle(r)
+        with _handle(cfg, verts, coef, omega=-1.0, asm_variant=av, kernel_path=path) as h:
+            L = h.info["n_levels"]
+            for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+                y = torch.empty(x.size, dtype=dt, device=DEV)
+                h.vmult(_t(x, dt).view(-1), y)
+                assert rel_err(_np(y), ref) < tol, (dt, "vmult")
+            h.set_omega(0, omega)
+            for dt, tol in ((torch.float64, 1e-11), (torch.float32, 2e-4)):
+                xs = _t(x0, dt)
+                h.smooth(_t(b, dt), xs, steps=2, level=0)
+                assert rel_err(_np(xs), sref) < tol, (dt, "smooth", av)
+            for l in range(L - 1):
+                h.set_omega(l, H.levels[L - 1 - l].omega)
+            for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+                z = torch.empty(r.size, dtype=dt, device=DEV)
+                h.vcycle(_t(r, dt), z)
+                assert rel_err(_np(z), vref) < tol, (dt, "vcycle", av)
+
+
+@pytest.mark.parametrize("name", BRICK_CASES)
+def test_brick_operator_levels(name):
+    """Every level's operator of a Cartesian hierarchy (bricks on the finest and p-levels, the
+    general kernel on h-levels, where the coefficient varies inside a cell) against the oracle, and
+    the brick path bitwise equal between two handles."""
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op, omegas=[1.0] * 16)
+    L = len(H.levels)
+    rng = np.random.default_rng(52)
+    with _handle(cfg, verts, coef, omega=0.5) as h, _handle(cfg, verts, coef, omega=0.5) as h2:
+        for l in range(L):
+            S = H.levels[L - 1 - l].S
+            xv = rng.standard_normal(S.shape[0])
+            y = torch.empty(xv.size, dtype=torch.float64, device=DEV)
+            h.vmult(_t(xv), y, level=l)
+            assert rel_err(_np(y), S @ xv) < 1e-12, l
+            y2 = torch.empty_like(y)
+            h2.vmult(_t(xv), y2, level=l)
+            assert torch.equal(y, y2), l
