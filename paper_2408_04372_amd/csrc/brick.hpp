@@ -73,7 +73,7 @@ struct RowWalk {
     }
   }
 };
-constexpr int ROW_BATCH = 16;
+constexpr int ROW_BATCH = 8;
 
 // Order LDS accesses of one wave: the LDS executes a wave's operations in issue order, so a value
 // written by one lane is visible to another lane of the same wave once the compiler keeps the
