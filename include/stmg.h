@@ -97,9 +97,12 @@ typedef struct {
   int32_t coarse_cells;    /* h-coarsening stops before a level has fewer cells per direction */
   int32_t vcycle_dtypes;   /* bit 0: build FP64 V-cycle data, bit 1: FP32; 0 = from precision */
   double omega;            /* > 0: relaxation used on every level; == 0: per level from eq. relaxation,
-                              omega_l = 2 / (lambda_max + lambda_min) of ASM * S_l (Arnoldi estimate);
-                              < 0: per level omega_l = |omega| / lambda_max (damps the top of the
-                              spectrum; the paper's rule leaves it undamped for high p) */
+                              omega_l = 2 / (lambda_max + lambda_min) of ASM * S_l (15-step Arnoldi
+                              estimate, clamped to (0, 1]); < 0: per level omega_l = |omega| /
+                              lambda_max.  omega = -1.5 is eq. relaxation with lambda_min read as
+                              lambda_max / 3: every eigenvalue in [lambda_max / 3, lambda_max] is
+                              damped by at least 2, independently of h, while with the true lambda_min
+                              (-> 0 as h -> 0) the top of the spectrum is hardly damped at Q4 */
   int32_t precision;       /* stmg_precision: preconditioner used by stmg_solve */
   int32_t restart;         /* FGMRES restart length m >= 1 */
   int32_t max_iter;        /* total FGMRES iterations allowed */
