@@ -175,6 +175,21 @@ stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const do
  * dtype 0: x, y double; dtype 1: float.  x and y must not alias. */
 stmg_status stmg_vmult(stmg_handle* h, int level, int dtype, const void* x, void* y);
 
+/* Bytes of the static per-device scratch used by stmg_vmult_noalloc. */
+#define STMG_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): y = S_level x as stmg_vmult defines it, computed on
+ * the per-cell path (each cell's contribution to its own slot, then a node gather in a fixed cell
+ * order) with the slots in a static device array of STMG_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  The call allocates nothing.
+ * Limit: the level's slots, ncells * n_t * (p+1)^dim values of dtype, must fit in
+ * STMG_SCRATCH_BYTES; a larger level is rejected with STMG_E_UNSUPPORTED.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a GPU (several streams or
+ * host threads) race and give wrong results; calls on one stream are ordered.  x, y device
+ * buffers as for stmg_vmult (must not alias).  Asynchronous on the handle's stream. */
+stmg_status stmg_vmult_noalloc(stmg_handle* h, int level, int dtype, const void* x, void* y);
+
 /* n_steps damped additive Schwarz steps (eq. vanka):
  * x <- x + omega_level * sum_T R_T^T [R_T S R_T^T]^{-1} R_T (b - S x),
  * blocks T = interior DoFs of one spatial cell x one time cell (eq. vanka0);

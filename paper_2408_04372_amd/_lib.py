@@ -84,6 +84,8 @@ _SIGS = {
     "stmg_create": ([ctypes.POINTER(CConfig), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "stmg_vmult": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "stmg_vmult_noalloc": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+                           ctypes.c_int),
     "stmg_smooth": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.c_int], ctypes.c_int),
     "stmg_vcycle": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -298,6 +300,12 @@ class Handle:
         self._sz(x, level); self._sz(y, level)
         d = _dtype_code(x)
         _check(self.lib.stmg_vmult(self.h, level, d, _ptr(x, x.dtype), _ptr(y, x.dtype)))
+        return y
+
+    def vmult_noalloc(self, x, y, level: int = 0):
+        self._sz(x, level); self._sz(y, level)
+        d = _dtype_code(x)
+        _check(self.lib.stmg_vmult_noalloc(self.h, level, d, _ptr(x, x.dtype), _ptr(y, x.dtype)))
         return y
 
     def smooth(self, b, x, steps: int = 1, level: int = 0):

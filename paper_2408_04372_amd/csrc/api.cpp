@@ -147,6 +147,7 @@ stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const do
     h->cfg = *cfg;
     h->stream = static_cast<hipStream_t>(hip_stream);
     STMG_HIP(hipGetDevice(&h->device));
+    stmg::noalloc_init(h->device);
     int dt = cfg->vcycle_dtypes;
     if (dt == 0) dt = cfg->precision == STMG_PREC_FP64 ? 1 : 2;
     h->want64 = (dt & 1) != 0;
@@ -167,6 +168,18 @@ stmg_status stmg_vmult(stmg_handle* h, int level, int dtype, const void* x, void
     if (x == y) stmg::fail(STMG_E_ARG, "x and y must not alias");
     if (dtype == STMG_F64) stmg::vmult<double>(h, level, (const double*)x, (double*)y);
     else stmg::vmult<float>(h, level, (const float*)x, (float*)y);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_vmult_noalloc(stmg_handle* h, int level, int dtype, const void* x, void* y) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, level);
+    check_dtype(h, dtype, false, level);
+    if (!x || !y) stmg::fail(STMG_E_ARG, "x or y is NULL");
+    if (x == y) stmg::fail(STMG_E_ARG, "x and y must not alias");
+    if (dtype == STMG_F64) stmg::vmult_noalloc<double>(h, level, (const double*)x, (double*)y);
+    else stmg::vmult_noalloc<float>(h, level, (const float*)x, (float*)y);
     return STMG_OK;
   });
 }

@@ -130,6 +130,9 @@ namespace stmg {
 // set-up and V-cycle entry points used by the C ABI (hierarchy.hip)
 void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff);
 template <class T> void vmult(stmg_handle* h, int level, const T* x, T* y);
+// operator apply through the static per-device scratch (noalloc.hip)
+void noalloc_init(int device);
+template <class T> void vmult_noalloc(stmg_handle* h, int level, const T* x, T* y);
 template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int steps);
 template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u);
 template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T* fine, bool accumulate);

@@ -77,6 +77,7 @@ def test_abi_version_and_null_arguments():
     assert lib.stmg_create(ctypes.byref(cfg), None, None, None, ctypes.byref(h)) == 1
     assert lib.stmg_create(None, None, None, None, ctypes.byref(h)) == 1
     assert lib.stmg_vmult(None, 0, 0, None, None) == 1
+    assert lib.stmg_vmult_noalloc(None, 0, 0, None, None) == 1
     assert lib.stmg_solve(None, None, None, None) == 1
     lib.stmg_destroy(None)
 
