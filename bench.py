@@ -51,9 +51,9 @@ TRAFFIC_PROFILES = {
     ("heat3d_32cube_Q4_perturbed_dG2_c8", "smoother"):
         ("k_asm_mfma_heat3d_q4_dg2_c8_hbm_traffic.md", ("asm.hip", "blas.hip", "device.hpp")),
     ("heat3d_128cube_Q4_dG1_c2", "operator"):
-        ("st_apply3_heat3d_128cube_q4_dg1_c2_hbm_traffic.md", ("op_apply.hip", "blas.hip", "device.hpp")),
+        ("st_apply3_brick_heat3d_128cube_q4_dg1_c2_hbm_traffic.md", ("op_brick.hip", "brick.hpp", "device.hpp")),
     ("heat3d_128cube_Q4_dG1_c2", "smoother"):
-        ("k_asm_fdm_heat3d_128cube_q4_dg1_c2_hbm_traffic.md", ("asm_fdm.hip", "blas.hip", "device.hpp")),
+        ("k_asm_fdm_brick_heat3d_128cube_q4_dg1_c2_hbm_traffic.md", ("asm_brick.hip", "brick.hpp", "device.hpp")),
 }
 
 
@@ -100,8 +100,9 @@ def algorithmic_terms(h, cfg, asm_variant, dtype_bytes=8):
     """Algorithmic bytes and flops of one finest-level apply of the operator and of the smoother.
 
     operator: read x and write y once (2 N_st s) plus per-cell data (rho_K, vertices);
-    flops per (cell, temporal DoF): 12 sum-factorisation sweeps of n^(d+1) FMA, 10 FMA per
-    quadrature point, temporal mixing at the n^d nodes.
+    flops per (cell, temporal DoF): on Cartesian meshes (one coefficient per cell, the brick
+    kernel) 8 separable 1D sweeps of n^(d+1) FMA, otherwise 12 sum-factorisation sweeps of
+    n^(d+1) FMA and 10 FMA per quadrature point; plus the temporal mixing at the n^d nodes.
     smoother: read r, read and write u (3 N_st s) plus stored cell factors (exact blocks) or
     rho_K (separable blocks)."""
     info = h.info
@@ -115,7 +116,10 @@ def algorithmic_terms(h, cfg, asm_variant, dtype_bytes=8):
     c = n_t // nt_cell
     meta = ncells * dtype_bytes + (int(np.prod([v + 1 for v in cfg.n_cells[:d]])) * d * 8 if cfg.perturb else 0)
     op_bytes = 2 * nst * dtype_bytes + meta
-    op_flops = ncells * (n_t * (2 * 12 * n ** (d + 1) + 2 * 10 * n ** d) + 2 * info["temporal_nnz"] * n ** d)
+    if d == 3 and not cfg.perturb:
+        op_flops = ncells * (n_t * 2 * 8 * n ** (d + 1) + 2 * info["temporal_nnz"] * n ** d)
+    else:
+        op_flops = ncells * (n_t * (2 * 12 * n ** (d + 1) + 2 * 10 * n ** d) + 2 * info["temporal_nnz"] * n ** d)
     if asm_variant == 0:
         asm_bytes = 3 * nst * dtype_bytes + ncells * (ns * ns + ns * nt_cell * nt_cell) * dtype_bytes
         asm_flops = ncells * (4 * ns * ns * n_t + 2 * ns * c * nt_cell * nt_cell)
@@ -403,9 +407,11 @@ def main():
         ach, peak, unit, frac = d["GBs"], HBM_PEAK_GBS, "GB/s", d["frac_hbm"]
     else:
         ach, peak, unit, frac = d["TFLOPs"], d["peak_flops"], "TFLOP/s", d["frac_flops"]
-    names = {"operator": "operator (st_apply3 over all cells + gather, finest level, FP64)",
-             "smoother": ("smoother (k_asm_fdm over all cells + gather, finest level, FP64)"
-                          if launch["asm_variant"] else
+    brick = cfg.dim == 3 and not cfg.perturb
+    names = {"operator": ("operator (st_apply3_brick, 8 brick colours, finest level, FP64)" if brick else
+                          "operator (st_apply3 over all cells + gather, finest level, FP64)"),
+             "smoother": ("smoother (k_asm_fdm_brick, 8 brick colours, finest level, FP64)"
+                          if (launch["asm_variant"] and brick) else
                           "smoother (k_asm_mfma over all cells + gather, finest level, FP64)")}
     roofline = {"kernel": names[dominant], "bound": d["bound"], "achieved": ach, "peak": peak, "unit": unit,
                 "frac": frac, "traffic": d["traffic"],

@@ -284,7 +284,7 @@ def test_slab_rhs_matches_oracle(name):
 
 @pytest.mark.parametrize("path", [0, 1, 2])
 @pytest.mark.parametrize("name", ["heat3d_q4_dg1_brick", "wave3d_q3_cgp2_brick", "heat3d_q2_dg1_c4_brick",
-                                  "heat3d_q2_dg1_pert", "heat2d_q2_dg1"])
+                                  "heat3d_q2_dg1_long", "heat3d_q2_dg1_pert", "heat2d_q2_dg1"])
 def test_kernel_paths(name, path):
     """Operator, smoother (exact and separable blocks where the mesh allows) and V-cycle through each
     way of summing cell contributions: bricks (0, Cartesian 3D levels), per-cell buffers (1) and
