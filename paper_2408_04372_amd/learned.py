@@ -133,7 +133,8 @@ def train_for_config(idx: int, solves: int, epochs: int, lr: float, cells: int =
     torch, si, Handle = _imports()
     tcfg = training_config(idx, cells)
     verts, coef = si.draw_problem(tcfg)
-    h = Handle(tcfg, verts, coef, vcycle_dtypes=3, precision=2, omega=-1.0, rtol=1e-11, max_iter=300)
+    # plain FP64 multigrid for the reference solves and the stationary iterations
+    h = Handle(tcfg, verts, coef, vcycle_dtypes=1, precision=0, omega=-1.0, rtol=1e-11, max_iter=300)
     ch = default_channels(tcfg.n_t)
     h.cnn_create(ch)
     rng = np.random.Generator(np.random.PCG64(7))
