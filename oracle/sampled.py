@@ -36,6 +36,7 @@ class Sampler:
         self.slab = temporal.slab(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau, cfg.t0)
         self._cache: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
         self._fdm = None
+        self._levels = None
 
     # node and cell numbering (computed per cell: the full tables would not fit at 10^8 nodes)
     def is_boundary(self, g: int) -> bool:
@@ -193,34 +194,123 @@ class Sampler:
         return out
 
 
+    # sampled grid transfers (Section 3.2) ------------------------------------------------------
+    def level_spaces(self) -> List[spatial.Space]:
+        """Spatial levels, finest (index 0) first, as in oracle.mg.level_spaces."""
+        if self._levels is None:
+            self._levels = mg.level_spaces(self.space)
+        return self._levels
+
+    def transfer_factors(self, level: int) -> List[np.ndarray]:
+        """Per direction, the 1D prolongation from level + 1 to level (dense, nodes_f x nodes_c).
+
+        The prolongation evaluates a coarse basis function at a fine node in the reference
+        coordinates of one coarse cell per direction, so its value is the product over the
+        directions of 1D values: P = P_{d-1} (x) ... (x) P_0 on the x-fastest node numbering.
+        Each factor is oracle.mg.prolongation on the 1D lattice of that direction."""
+        fine, coarse = self.level_spaces()[level], self.level_spaces()[level + 1]
+        out = []
+        for d in range(fine.dim):
+            f1 = spatial.Space(dim=1, cells=(fine.cells[d],), p=fine.p, verts=None, lo=(0.0,), hi=(1.0,),
+                               coef_fine=np.ones(1), fine_cells=(fine.cells[d],))
+            c1 = spatial.Space(dim=1, cells=(coarse.cells[d],), p=coarse.p, verts=None, lo=(0.0,), hi=(1.0,),
+                               coef_fine=np.ones(1), fine_cells=(fine.cells[d],))
+            out.append(mg.prolongation(c1, f1).toarray())
+        return out
+
+    @staticmethod
+    def _coords(g: int, nodes) -> List[int]:
+        out = []
+        for m in nodes:
+            out.append(g % m)
+            g //= m
+        return out
+
+    def prolong_entries(self, ec: np.ndarray, level: int, samples) -> np.ndarray:
+        """(P e_c)[i, g] at fine-level nodes: e_c of shape (n_t, N_x of level + 1), Dirichlet
+        values of e_c read as zero, zero at fine Dirichlet nodes (oracle.mg.Hierarchy.prolong)."""
+        fine, coarse = self.level_spaces()[level], self.level_spaces()[level + 1]
+        ec = ec.reshape(-1, coarse.n_x)
+        P1 = self.transfer_factors(level)
+        out = np.zeros(len(samples))
+        for s, (i, g) in enumerate(samples):
+            xf = self._coords(g, fine.nodes)
+            if any(x == 0 or x == m - 1 for x, m in zip(xf, fine.nodes)):
+                continue
+            cols = [np.nonzero(P1[d][xf[d]])[0] for d in range(fine.dim)]
+            val = 0.0
+            for cc in np.array(np.meshgrid(*cols, indexing="ij")).reshape(fine.dim, -1).T:
+                if any(c == 0 or c == m - 1 for c, m in zip(cc, coarse.nodes)):
+                    continue
+                w, gc, stride = 1.0, 0, 1
+                for d in range(fine.dim):
+                    w *= P1[d][xf[d], cc[d]]
+                    gc += int(cc[d]) * stride
+                    stride *= coarse.nodes[d]
+                val += w * ec[i, gc]
+            out[s] = val
+        return out
+
+    def restrict_entries(self, rf: np.ndarray, level: int, samples) -> np.ndarray:
+        """(P^T r_f)[i, g] at nodes of level + 1: r_f of shape (n_t, N_x of level), Dirichlet
+        values of r_f read as zero, zero at coarse Dirichlet nodes (oracle.mg.Hierarchy.restrict)."""
+        fine, coarse = self.level_spaces()[level], self.level_spaces()[level + 1]
+        rf = rf.reshape(-1, fine.n_x)
+        P1 = self.transfer_factors(level)
+        out = np.zeros(len(samples))
+        for s, (i, g) in enumerate(samples):
+            xc = self._coords(g, coarse.nodes)
+            if any(x == 0 or x == m - 1 for x, m in zip(xc, coarse.nodes)):
+                continue
+            rows = [np.nonzero(P1[d][:, xc[d]])[0] for d in range(fine.dim)]
+            val = 0.0
+            for ff in np.array(np.meshgrid(*rows, indexing="ij")).reshape(fine.dim, -1).T:
+                if any(f == 0 or f == m - 1 for f, m in zip(ff, fine.nodes)):
+                    continue
+                w, gf, stride = 1.0, 0, 1
+                for d in range(fine.dim):
+                    w *= P1[d][ff[d], xc[d]]
+                    gf += int(ff[d]) * stride
+                    stride *= fine.nodes[d]
+                val += w * rf[i, gf]
+            out[s] = val
+        return out
+
+
 def sample_points(cfg, n_inner: int, n_boundary: int, seed: int):
-    """(temporal DoF, node) pairs: interior nodes of every kind (cell corners, edges, faces,
-    cell interiors) and a few Dirichlet nodes, drawn from a seeded generator."""
+    """(temporal DoF, node) pairs on the finest level: interior nodes of every kind (cell
+    corners, edges, faces, cell interiors) and a few Dirichlet nodes, drawn from a seeded
+    generator."""
+    return lattice_points(cfg.p, cfg.n_cells[: cfg.dim], cfg.n_t, n_inner, n_boundary, seed)
+
+
+def lattice_points(p: int, cells, n_t: int, n_inner: int, n_boundary: int, seed: int):
+    """Like sample_points for any Q_p lattice of `cells` cells per direction and n_t planes."""
     rng = np.random.default_rng(seed)
-    nodes = [p * c + 1 for p, c in zip([cfg.p] * cfg.dim, cfg.n_cells[: cfg.dim])]
-    n_t = cfg.n_t
+    dim = len(cells)
+    nodes = [p * c + 1 for c in cells]
     out = []
     for t in range(n_inner):
         kind = t % 4          # number of coordinates that sit on a cell boundary (0..3, capped at dim)
         coords = []
-        for d in range(cfg.dim):
-            on = d < min(kind, cfg.dim)
+        for d in range(dim):
+            on = d < min(kind, dim)
             while True:
                 x = int(rng.integers(1, nodes[d] - 1))
-                if (x % cfg.p == 0) == on or cfg.p == 1:
+                if (x % p == 0) == on or p == 1:
                     break
             coords.append(x)
         g, stride = 0, 1
-        for d in range(cfg.dim):
+        for d in range(dim):
             g += coords[d] * stride
             stride *= nodes[d]
         out.append((int(rng.integers(0, n_t)), g))
     for _ in range(n_boundary):
         coords = [int(rng.integers(0, m)) for m in nodes]
-        d = int(rng.integers(0, cfg.dim))
+        d = int(rng.integers(0, dim))
         coords[d] = 0 if rng.random() < 0.5 else nodes[d] - 1
         g, stride = 0, 1
-        for dd in range(cfg.dim):
+        for dd in range(dim):
             g += coords[dd] * stride
             stride *= nodes[dd]
         out.append((int(rng.integers(0, n_t)), g))

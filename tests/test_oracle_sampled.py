@@ -63,3 +63,41 @@ def test_sampled_separable_step_matches_blocks():
     got = smp.asm_entries(x, 0.4, pts, separable=True)
     ref = np.array([u[i, g] for i, g in pts])
     assert np.allclose(got, ref, rtol=1e-10, atol=1e-10 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("cfg", [
+    si.Config(dim=3, problem=0, time_method=0, p=4, k=1, n_time_cells=2, n_cells=(4, 6, 4), tau=0.05,
+              perturb=0.1, coef="lognormal", coef_sigma=1.0, seed=45),
+    si.Config(dim=3, problem=1, time_method=1, p=3, k=2, n_time_cells=1, n_cells=(4, 4, 8), tau=0.04,
+              coef="lognormal", coef_sigma=0.5, seed=46),
+    si.Config(dim=2, problem=0, time_method=0, p=2, k=0, n_time_cells=2, n_cells=(8, 4, 1), tau=0.05,
+              coef="lognormal", coef_sigma=0.5, seed=47),
+], ids=["heat3d_q4_perturbed", "wave3d_q3", "heat2d_q2"])
+def test_sampled_transfers_match_hierarchy(cfg):
+    """Single entries of P e and P^T r on every level pair (p- and h-transfers) equal those of the
+    assembled transfers of oracle.mg.Hierarchy."""
+    verts, coef = si.draw_problem(cfg)
+    op = spacetime.from_config(cfg, verts, coef)
+    H = mg.Hierarchy(op, omegas=[1.0] * 16)
+    smp = sampled.Sampler(cfg, verts, coef)
+    spaces = smp.level_spaces()
+    L = len(H.levels)
+    assert len(spaces) == L and L >= 3
+    rng = np.random.default_rng(11)
+    kinds = set()
+    for l in range(L - 1):
+        io = L - 1 - l
+        fine, coarse = spaces[l], spaces[l + 1]
+        assert H.levels[io].op.n_x == fine.n_x and H.levels[io - 1].op.n_x == coarse.n_x
+        kinds.add("p" if fine.cells == coarse.cells else "h")
+        ec = rng.standard_normal((cfg.n_t, coarse.n_x))
+        rf = rng.standard_normal((cfg.n_t, fine.n_x))
+        pe = H.prolong(io, ec.ravel()).reshape(cfg.n_t, fine.n_x)
+        rr = H.restrict(io, rf.ravel()).reshape(cfg.n_t, coarse.n_x)
+        ptf = sampled.lattice_points(fine.p, fine.cells, cfg.n_t, 40, 8, seed=l)
+        ptc = sampled.lattice_points(coarse.p, coarse.cells, cfg.n_t, 40, 8, seed=100 + l)
+        got = smp.prolong_entries(ec, l, ptf)
+        assert np.allclose(got, [pe[i, g] for i, g in ptf], rtol=1e-13, atol=1e-13 * np.abs(pe).max())
+        got = smp.restrict_entries(rf, l, ptc)
+        assert np.allclose(got, [rr[i, g] for i, g in ptc], rtol=1e-13, atol=1e-13 * np.abs(rr).max())
+    assert kinds == {"p", "h"}
