@@ -226,7 +226,8 @@ void launch_fdm_brick(const GeomDesc& g, int n_t, const double* Mtau, const doub
   A.overwrite = u_zero ? 1 : 0;
   A.n_t = n_t;
   BrickPlan pl;
-  if (!plan_brick(g, n_t, n_t / NTC, NTC * N, sizeof(T), NTC * N * N, sizeof(T) * 3 * 4 * (N * N + N), pl))
+  static const int vgprs = kernel_vgprs(k_asm_fdm_brick<T, N, NTC>);
+  if (!plan_brick(g, n_t, n_t / NTC, NTC * N, sizeof(T), NTC * N * N, sizeof(T) * 3 * 4 * (N * N + N), vgprs, pl))
     fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs of the smoother");
   BrickLaunch L[8];
   brick_launches(g, pl, L);

@@ -166,29 +166,54 @@ struct BrickPlan {
   size_t lds = 0;
 };
 
-// Brick size: the largest product of the share of owned nodes, lane use and LDS occupancy (eight
-// waves per CU count as full), with at most 8 waves, every work item of the brick (items_per_cell
-// per cell, one team of team_lanes lanes each, teams never straddling a wave) in one round of teams, and LDS (n_t planes of the box,
-// team_scratch values per team, plus `extra` bytes) within budget.
+// Registers of a kernel's waves (VGPRs), read once per instantiation; 128 when HIP cannot say.
+template <class K>
+inline int kernel_vgprs(K kernel) {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess || a.numRegs <= 0) {
+    (void)hipGetLastError();
+    return 128;
+  }
+  return a.numRegs;
+}
+
+// Brick size: the largest product of
+//   - the share of owned nodes in the staged box (halo nodes are read twice),
+//   - the share of a lattice row's bytes in the cache lines it touches (rows of NBd[0] nodes plus
+//     about half a 128-byte line of neighbours' nodes),
+//   - the lane use of the teams, and
+//   - the occupancy: resident waves per CU (workgroups limited by LDS, 160 KB per CU, and by the
+//     kernel's VGPRs, 512 per lane and SIMD) against 8, times 3/4 when only one workgroup fits a CU
+//     (its staging, compute and write-back phases then run back to back),
+// with at most 8 waves, every work item of the brick (items_per_cell per cell, one team of
+// team_lanes lanes each, teams never straddling a wave) in one round of teams, and LDS (n_t planes
+// of the box, team_scratch values per team, plus `extra` bytes) within 72 KB.
 inline bool plan_brick(const GeomDesc& g, int n_t, int items_per_cell, int team_lanes, size_t elem,
-                       int team_scratch, size_t extra, BrickPlan& out) {
+                       int team_scratch, size_t extra, int vgprs, BrickPlan& out) {
   const int p = g.p;
   const int tpw = 64 / team_lanes;
-  static const int cand[][3] = {{4, 3, 2}, {4, 2, 2}, {3, 3, 2}, {3, 2, 2}, {2, 2, 2}, {3, 2, 1},
-                                {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+  const int vg = std::max(8, (vgprs + 7) / 8 * 8);
+  const int waves_simd = std::max(1, std::min(8, 512 / vg));
+  static const int cand[][3] = {{4, 3, 2}, {4, 2, 2}, {3, 3, 2}, {3, 2, 2}, {2, 3, 2}, {2, 2, 2}, {6, 2, 1},
+                                {4, 3, 1}, {4, 2, 1}, {3, 3, 1}, {3, 2, 1}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
   double best = -1.0;
   for (auto& c : cand) {
     int B[3] = {std::min(c[0], g.nc[0]), std::min(c[1], g.nc[1]), std::min(c[2], g.nc[2])};
     const long long items = (long long)B[0] * B[1] * B[2] * items_per_cell;
     const int waves = (int)((items + tpw - 1) / tpw);
     if (waves > 8) continue;
-    const long long nb = (long long)(p * B[0] + 1) * (p * B[1] + 1) * (p * B[2] + 1);
+    const int nbd0 = p * B[0] + 1;
+    const long long nb = (long long)nbd0 * (p * B[1] + 1) * (p * B[2] + 1);
     const size_t lds = elem * ((size_t)n_t * nb + (size_t)waves * tpw * team_scratch) + extra;
     if (lds > 72 * 1024) continue;
     const double owned = (double)(p * B[0]) * (p * B[1]) * (p * B[2]) / (double)nb;
+    const double row = (double)(nbd0 * elem) / (double)(nbd0 * elem + 64);
     const double use = (double)items / ((double)waves * tpw);
-    const double occ = std::min(1.0, (double)((160 * 1024) / lds) * waves / 8.0);
-    const double score = owned * use * occ;
+    const int simd_waves = (waves + 3) / 4;                    // waves of one workgroup per SIMD
+    const int wgs = std::min((int)((160 * 1024) / lds), std::min(4 * waves_simd / waves, waves_simd / simd_waves));
+    if (wgs < 1) continue;
+    const double occ = std::min(1.0, (double)(wgs * waves) / 8.0) * (wgs >= 2 ? 1.0 : 0.75);
+    const double score = owned * row * use * occ;
     if (score > best + 1e-9) {
       best = score;
       out.B[0] = B[0]; out.B[1] = B[1]; out.B[2] = B[2];

@@ -18,6 +18,13 @@ namespace stmg {
 struct Transfer1D {           // one direction of P (coarse -> fine) or R = P^T (fine -> coarse)
   int len_out = 0, nnz = 0, max_row = 0;   // rows, entries, most entries in one row
   DevBuf ptr, col, w64, w32;
+  std::vector<int> ptr_h, col_h;          // host copies (tables of the fused transfer)
+  std::vector<double> w_h;
+};
+
+struct Fused3 {               // tables of the fused 3D transfer (see Tensor3Plan)
+  Tensor3Plan pl;
+  DevBuf lo[3], hi[3], col[3], w64[3], w32[3];
 };
 
 template <class T>
@@ -57,6 +64,7 @@ struct Level {
   double omega = 1.0;
   // transfer between this level (fine) and level+1 (coarse)
   std::array<Transfer1D, 3> P, R;
+  Fused3 PF, RF;              // fused 3D transfers (tiles and padded tables)
   // coarsest level
   DevBuf cidx;                // interior DoF indices (full-lattice space-time index)
   int cm = 0;

@@ -189,6 +189,9 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
     }
     T.len_out = (int)L.size();
     T.nnz = (int)col.size();
+    T.ptr_h = ptr;
+    T.col_h = col;
+    T.w_h = w;
     T.ptr = upload(ptr, s);
     T.col = upload(col, s);
     T.w64 = upload(w, s);
@@ -196,6 +199,104 @@ void transfer_1d(int pc, int ncc, int pf, int ncf, Transfer1D& P, Transfer1D& R,
   };
   up(rows, P);
   up(cols, R);
+}
+
+// Per-tile input range of a banded 1D factor: lo[t], hi[t] over the rows of tile t (tiles of
+// `tile` consecutive output rows; lo > hi when every row of the tile is empty).
+void tile_ranges(const Transfer1D& A, int tile, std::vector<int>& lo, std::vector<int>& hi) {
+  const int nt = (A.len_out + tile - 1) / tile;
+  lo.assign(nt, 0);
+  hi.assign(nt, -1);
+  for (int t = 0; t < nt; ++t) {
+    int l = 1 << 30, h = -1;
+    for (int r = t * tile; r < std::min(A.len_out, (t + 1) * tile); ++r) {
+      const int k0 = A.ptr_h[r], k1 = A.ptr_h[r + 1];
+      if (k1 > k0) { l = std::min(l, A.col_h[k0]); h = std::max(h, A.col_h[k1 - 1]); }
+    }
+    if (h >= l) { lo[t] = l; hi[t] = h; }
+  }
+}
+
+// Tiles and tables of the fused 3D transfer with factors A[3] (see Tensor3Plan): the x-y tile
+// with the most output nodes per workgroup (up to 256), ties broken by a smaller input patch per
+// output (by at least 10 %, else the longer x rows), with the patch within 2048 nodes; z chunks of 16 planes (4 on short axes).  Not ok when
+// an x or y row is longer than 10 entries (R of an h-transfer at p >= 3) or no tile fits.
+void build_fused3(const std::array<Transfer1D, 3>& A, Fused3& F, hipStream_t s) {
+  Tensor3Plan& best = F.pl;
+  best = Tensor3Plan();
+  int kmax = 2;
+  for (int d = 0; d < 2; ++d) kmax = std::max(kmax, A[d].max_row);
+  static const int ks[] = {2, 3, 4, 5, 6, 8, 10};
+  int kp = 0;
+  for (int k : ks)
+    if (k >= kmax) { kp = k; break; }
+  if (kp == 0) return;                      // rows too long: 1D sweeps instead
+  auto span = [&](int d, int tile) {
+    std::vector<int> lo, hi;
+    tile_ranges(A[d], tile, lo, hi);
+    int m = 1;
+    for (size_t i = 0; i < lo.size(); ++i) m = std::max(m, hi[i] - lo[i] + 1);
+    return m;
+  };
+  static const int cand[][2] = {{64, 4}, {32, 8}, {16, 16}, {64, 2}, {32, 4}, {16, 8}, {8, 8}, {64, 1}, {32, 2},
+                                {16, 4}, {8, 4}, {4, 4}, {16, 2}, {8, 2}, {4, 2}, {2, 2}, {8, 1}, {4, 1}, {2, 1}, {1, 1}};
+  long long bestn = 0;
+  double bestr = 0.0;
+  for (auto& c : cand) {
+    int cap0 = 1, cap1 = 1;
+    while (cap0 < A[0].len_out) cap0 *= 2;
+    while (cap1 < A[1].len_out) cap1 *= 2;
+    if (c[0] > cap0 || c[1] > cap1) continue;
+    const int S0 = span(0, c[0]), S1 = span(1, c[1]);
+    if ((long long)S0 * S1 > 2048) continue;
+    const long long n = (long long)c[0] * c[1];
+    const double r = (double)S0 * S1 / (double)n;
+    if (n > bestn || (n == bestn && r < 0.9 * bestr)) {      // longer x rows unless 10 % fewer reads
+      bestn = n;
+      bestr = r;
+      best.T[0] = c[0]; best.T[1] = c[1];
+      best.S[0] = S0; best.S[1] = S1;
+    }
+  }
+  if (bestn == 0) return;
+  best.T[2] = A[2].len_out >= 32 ? 16 : 4;
+  best.S[2] = span(2, best.T[2]);
+  best.kmax = kp;
+  while ((1 << best.lg[0]) < best.T[0]) ++best.lg[0];
+  std::vector<int> lo, hi;
+  for (int d = 0; d < 3; ++d) {
+    tile_ranges(A[d], best.T[d], lo, hi);
+    best.nt[d] = (int)lo.size();
+    std::vector<int> col;
+    std::vector<double> w;
+    if (d < 2) {
+      col.assign((size_t)A[d].len_out * kp, 0);
+      w.assign((size_t)A[d].len_out * kp, 0.0);
+      for (int r = 0; r < A[d].len_out; ++r) {
+        const int t = r / best.T[d];
+        for (int k = A[d].ptr_h[r], q = 0; k < A[d].ptr_h[r + 1]; ++k, ++q) {
+          col[(size_t)r * kp + q] = A[d].col_h[k] - lo[t];
+          w[(size_t)r * kp + q] = A[d].w_h[k];
+        }
+      }
+    } else {
+      // dense weights of each chunk: w[chunk][k][j] multiplies input plane lo[chunk] + j
+      const int TZ = best.T[2], SZ = best.S[2];
+      w.assign((size_t)best.nt[2] * TZ * SZ, 0.0);
+      for (int r = 0; r < A[d].len_out; ++r) {
+        const int t = r / TZ, k0 = r - t * TZ;
+        for (int k = A[d].ptr_h[r]; k < A[d].ptr_h[r + 1]; ++k)
+          w[((size_t)t * TZ + k0) * SZ + (A[d].col_h[k] - lo[t])] = A[d].w_h[k];
+      }
+    }
+    std::vector<float> wf(w.begin(), w.end());
+    F.lo[d] = upload(lo, s);
+    F.hi[d] = upload(hi, s);
+    if (!col.empty()) F.col[d] = upload(col, s);
+    F.w64[d] = upload(w, s);
+    F.w32[d] = upload(wf, s);
+  }
+  best.ok = true;
 }
 
 void init_geom(Level& L, int dim, const stmg_config& cfg) {
@@ -724,6 +825,10 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
       continue;
     }
     for (int d = 0; d < dim; ++d) transfer_1d(C.p, C.cells[d], F.p, F.cells[d], F.P[d], F.R[d], s);
+    if (dim == 3) {
+      build_fused3(F.P, F.PF, s);
+      build_fused3(F.R, F.RF, s);
+    }
   }
   // smoothers, work vectors, coarse inverse
   for (size_t l = 0; l < h->levels.size(); ++l) {
@@ -819,6 +924,14 @@ template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int 
   }
 }
 
+template <class T> std::array<T3Axis, 3> fused_axes(const Fused3& F) {
+  std::array<T3Axis, 3> a;
+  for (int d = 0; d < 3; ++d)
+    a[d] = T3Axis{F.lo[d].as<int>(), F.hi[d].as<int>(), F.col[d].as<int>(),
+                  std::is_same<T, double>::value ? F.w64[d].get() : F.w32[d].get()};
+  return a;
+}
+
 template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T* fine, bool accumulate) {
   Level& F = *h->levels[level];
   Level& C = *h->levels[level + 1];
@@ -831,6 +944,10 @@ template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T
   }
   int n_t = F.n_t();
   int dim = F.g.dim;
+  if (dim == 3 && F.PF.pl.ok) {
+    tensor3<T>(coarse, fine, n_t, C.g.nn, F.g.nn, F.PF.pl, fused_axes<T>(F.PF).data(), accumulate, s);
+    return;
+  }
   const T* in = coarse;
   int dims[3] = {C.g.nn[0], C.g.nn[1], C.g.nn[2]};
   T* bufs[2] = {d.tmpA.template as<T>(), d.tmpB.template as<T>()};
@@ -857,6 +974,10 @@ template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* c
   }
   int n_t = F.n_t();
   int dim = F.g.dim;
+  if (dim == 3 && F.RF.pl.ok) {
+    tensor3<T>(fine, coarse, n_t, F.g.nn, C.g.nn, F.RF.pl, fused_axes<T>(F.RF).data(), false, s);
+    return;
+  }
   const T* in = fine;
   int dims[3] = {F.g.nn[0], F.g.nn[1], F.g.nn[2]};
   T* bufs[2] = {d.tmpA.template as<T>(), d.tmpB.template as<T>()};

@@ -93,6 +93,32 @@ template <class T>
 void sweep1d(const T* in, T* out, int n_t, const int in_dims[3], int ax, int out_len, const int* ptr,
              const int* col, const T* w, int nnz, int max_row, bool accumulate, hipStream_t s);
 
+// Fused 3D tensor-product transfer (transfer.hip): out (+)= (Az (x) Ay (x) Ax) in on each of n_t
+// planes, with banded 1D factors.  Outputs are tiled in T[0] x T[1] boxes in x and y (T[0] a power
+// of two, T[0] T[1] <= 256) and chunks of T[2] (16 or 4) planes in z.  Tables per axis (T3Axis):
+// for every tile (x, y) or chunk (z) the first and last input index it reads (lo > hi: all its rows
+// are empty); for x and y every output row's kmax (column - lo of the row's tile, weight) pairs,
+// padded with zero weights and column 0; for z the chunk's dense weights [chunk][T[2]][S[2]].  S is
+// the largest input span of a tile per axis (S[0] S[1] <= 2048).  ok is false when no tile fits or
+// an x or y row is longer than the kernel's largest kmax; then the transfer runs as 1D sweeps.
+struct Tensor3Plan {
+  int T[3] = {1, 1, 1};
+  int lg[3] = {0, 0, 0};
+  int S[3] = {1, 1, 1};
+  int nt[3] = {1, 1, 1};
+  int kmax = 2;
+  bool ok = false;
+};
+struct T3Axis {
+  const int* lo;      // [tiles]
+  const int* hi;      // [tiles]
+  const int* col;     // x, y: [rows][kmax]; z: unused
+  const void* w;      // x, y: [rows][kmax]; z: [chunks][T[2]][S[2]]; element type T
+};
+template <class T>
+void tensor3(const T* in, T* out, int n_t, const int in_dims[3], const int out_dims[3], const Tensor3Plan& pl,
+             const T3Axis ax[3], bool accumulate, hipStream_t s);
+
 // Temporal transfer on the interior nodes of one spatial lattice of nx nodes (transfer.hip):
 // mode 0: out = (P (x) I) in, 1: out += (P (x) I) in, 2: out = (P^T (x) I) in, with P the dense
 // (nf x nc) temporal prolongation; vectors are [plane][node], Dirichlet nodes give zero.

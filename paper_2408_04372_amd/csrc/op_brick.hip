@@ -15,6 +15,8 @@
 // wave) owns one (cell, output temporal DoF); lane t first holds the y = t plane of the cell
 // ([z][x]: x and z sweeps are lane local), then, after a per-x-slice exchange through a small LDS
 // scratch, the z = t plane ([y][x]: y sweeps lane local).
+#include <type_traits>
+
 #include "brick.hpp"
 
 namespace stmg {
@@ -265,13 +267,17 @@ void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T
   const size_t csr = sizeof(T) * (size_t)(tp.mnnz + tp.nnnz) +
                      sizeof(int) * (size_t)(2 * (tp.n_t + 1) + tp.mnnz + tp.nnnz);
   BrickPlan pl;
-  if (!plan_brick(g, tp.n_t, tp.n_t, g.n, sizeof(T), 2 * g.n * g.n, csr, pl))
-    fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs");
+  auto run = [&](auto tag, int vgprs) {
+    constexpr int N = decltype(tag)::value;
+    if (!plan_brick(g, tp.n_t, tp.n_t, N, sizeof(T), 2 * N * N, csr, vgprs, pl))
+      fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs");
+    launch_brick<T, N>(g, ct, tp, x, y, scale, base, overwrite, pl, s);
+  };
   switch (g.n) {
-    case 2: launch_brick<T, 2>(g, ct, tp, x, y, scale, base, overwrite, pl, s); break;
-    case 3: launch_brick<T, 3>(g, ct, tp, x, y, scale, base, overwrite, pl, s); break;
-    case 4: launch_brick<T, 4>(g, ct, tp, x, y, scale, base, overwrite, pl, s); break;
-    case 5: launch_brick<T, 5>(g, ct, tp, x, y, scale, base, overwrite, pl, s); break;
+    case 2: { static const int v = kernel_vgprs(st_apply3_brick<T, 2>); run(std::integral_constant<int, 2>(), v); break; }
+    case 3: { static const int v = kernel_vgprs(st_apply3_brick<T, 3>); run(std::integral_constant<int, 3>(), v); break; }
+    case 4: { static const int v = kernel_vgprs(st_apply3_brick<T, 4>); run(std::integral_constant<int, 4>(), v); break; }
+    case 5: { static const int v = kernel_vgprs(st_apply3_brick<T, 5>); run(std::integral_constant<int, 5>(), v); break; }
     default: fail(STMG_E_UNSUPPORTED, "p must be 1..4");
   }
 }

@@ -97,7 +97,142 @@ __global__ __launch_bounds__(256) void k_time_transfer(const T* __restrict__ P, 
   }
 }
 
+// Fused tensor-product transfer: out (+)= (Az (x) Ay (x) Ax) in on every temporal plane.  A
+// workgroup owns TX x TY output nodes of one plane in x and y (one per thread) and a chunk of TZC
+// output z planes, and streams through the input z planes the chunk depends on: each input plane's
+// patch (SY x SX nodes, prefetched into registers while the previous plane is contracted) is staged
+// in LDS, contracted along x and y, and added into the TZC accumulators of every thread with the
+// chunk's dense z weights.  Every input node is read once per tile column (plus the x-y halo) and
+// every output node written once; the three sweeps of sweep1d and their intermediate vectors are
+// gone.  Tile ranges, padded rows and the z weights come from host-built tables.
+constexpr int T3_PF = 8;                 // patch values per thread (patch <= 8 * 256 nodes)
+
+template <class T, int KMAX, int TZC>
+__global__ __launch_bounds__(256) void k_tensor3(const T* __restrict__ in, T* __restrict__ out, int in0, int in1,
+                                                 int in2, int out0, int out1, int out2, T3Axis ax, T3Axis ay, T3Axis az,
+                                                 int lgx, int TY, int SX, int SZ, int ntx, int nty, int accumulate) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int TX = 1 << lgx;
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x, txi = tile % ntx, tyz = tile / ntx, tyi = tyz % nty, tzi = tyz / nty;
+  const int ox0 = txi << lgx, oy0 = tyi * TY, oz0 = tzi * TZC;
+  const int fx = tid & (TX - 1), fy = tid >> lgx;
+  const bool own = fy < TY && ox0 + fx < out0 && oy0 + fy < out1;
+  T* dst = out + (long long)blockIdx.y * out0 * out1 * out2 + ((long long)oz0 * out1 + (oy0 + fy)) * out0 + (ox0 + fx);
+  const long long zstride = (long long)out0 * out1;
+  const int lx = ax.lo[txi], ly = ay.lo[tyi], lz = az.lo[tzi];
+  const int bx = ax.hi[txi] - lx + 1, by = ay.hi[tyi] - ly + 1, bz = az.hi[tzi] - lz + 1;
+  T acc[TZC];
+#pragma unroll
+  for (int k = 0; k < TZC; ++k) acc[k] = 0;
+  if (bx > 0 && by > 0 && bz > 0) {
+    T* blk = reinterpret_cast<T*>(smem_raw);               // [by][SX] input patch
+    T* t1 = blk + (size_t)by * SX;                          // [by][TX]
+    const T* src = in + (long long)blockIdx.y * ((long long)in0 * in1 * in2) + ((long long)lz * in1 + ly) * in0 + lx;
+    // patch offsets of this thread (fixed for every input plane)
+    int goff[T3_PF], loff[T3_PF];
+    const int np = bx * by;
+#pragma unroll
+    for (int k = 0; k < T3_PF; ++k) {
+      const int e = tid + k * 256;
+      const int r = e / bx, ix = e - r * bx;
+      goff[k] = r * in0 + ix;
+      loff[k] = e < np ? r * SX + ix : -1;
+    }
+    // rows of Ax and Ay for this thread
+    T wx[KMAX], wy[KMAX];
+    int cx[KMAX], cy[KMAX];
+    const int rx = ox0 + fx, ry = oy0 + fy;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      wx[q] = rx < out0 ? static_cast<const T*>(ax.w)[(size_t)rx * KMAX + q] : (T)0;
+      cx[q] = rx < out0 ? ax.col[(size_t)rx * KMAX + q] : 0;
+      wy[q] = own ? static_cast<const T*>(ay.w)[(size_t)ry * KMAX + q] : (T)0;
+      cy[q] = own ? ay.col[(size_t)ry * KMAX + q] : 0;
+    }
+    const T* zw = static_cast<const T*>(az.w) + (size_t)tzi * TZC * SZ;   // [TZC][SZ] dense z weights
+    const long long pstride = (long long)in0 * in1;
+    T pv[T3_PF];
+#pragma unroll
+    for (int k = 0; k < T3_PF; ++k) pv[k] = loff[k] >= 0 ? src[goff[k]] : (T)0;
+    for (int iz = 0; iz < bz; ++iz) {
+#pragma unroll
+      for (int k = 0; k < T3_PF; ++k)
+        if (loff[k] >= 0) blk[loff[k]] = pv[k];
+      if (iz + 1 < bz) {
+        const T* nsrc = src + (iz + 1) * pstride;
+#pragma unroll
+        for (int k = 0; k < T3_PF; ++k) pv[k] = loff[k] >= 0 ? nsrc[goff[k]] : (T)0;
+      }
+      __syncthreads();
+      for (int e = tid; e < by * TX; e += 256) {
+        const T* b = blk + (size_t)(e >> lgx) * SX;
+        T a = 0;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) a += wx[q] * b[cx[q]];
+        t1[e] = a;
+      }
+      __syncthreads();
+      if (own) {
+        T v = 0;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) v += wy[q] * t1[(size_t)cy[q] * TX + fx];
+#pragma unroll
+        for (int k = 0; k < TZC; ++k) acc[k] += zw[k * SZ + iz] * v;
+      }
+    }
+  }
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < TZC; ++k)
+      if (oz0 + k < out2) {
+        T* o = dst + k * zstride;
+        if (accumulate) *o += acc[k];
+        else *o = acc[k];
+      }
+  }
+}
+
 }  // namespace
+
+template <class T>
+void tensor3(const T* in, T* out, int n_t, const int in_dims[3], const int out_dims[3], const Tensor3Plan& pl,
+             const T3Axis ax[3], bool accumulate, hipStream_t s) {
+  if ((long long)out_dims[0] * out_dims[1] * out_dims[2] * n_t <= 0) return;
+  if (!pl.ok) fail(STMG_E_STATE, "fused transfer without a plan");
+  const long long tiles = (long long)pl.nt[0] * pl.nt[1] * pl.nt[2];
+  if (tiles >= (1LL << 24) || n_t > 65535) fail(STMG_E_UNSUPPORTED, "lattice too large for the transfer kernel");
+  if (pl.T[0] * pl.T[1] > 256 || (1 << pl.lg[0]) != pl.T[0] || pl.S[0] * pl.S[1] > T3_PF * 256)
+    fail(STMG_E_STATE, "fused transfer tile");
+  const size_t lds = sizeof(T) * ((size_t)pl.S[1] * pl.S[0] + (size_t)pl.S[1] * pl.T[0]);
+  dim3 grid((unsigned)tiles, (unsigned)n_t);
+  const int acc = accumulate ? 1 : 0;
+#define STMG_T3(K, Z) hipLaunchKernelGGL((k_tensor3<T, K, Z>), grid, dim3(256), lds, s, in, out, in_dims[0], in_dims[1], \
+                                         in_dims[2], out_dims[0], out_dims[1], out_dims[2], ax[0], ax[1], ax[2], \
+                                         pl.lg[0], pl.T[1], pl.S[0], pl.S[2], pl.nt[0], pl.nt[1], acc)
+#define STMG_T3K(Z)                      \
+  switch (pl.kmax) {                     \
+    case 2: STMG_T3(2, Z); break;        \
+    case 3: STMG_T3(3, Z); break;        \
+    case 4: STMG_T3(4, Z); break;        \
+    case 5: STMG_T3(5, Z); break;        \
+    case 6: STMG_T3(6, Z); break;        \
+    case 8: STMG_T3(8, Z); break;        \
+    case 10: STMG_T3(10, Z); break;      \
+    default: fail(STMG_E_UNSUPPORTED, "transfer row length"); \
+  }
+  if (pl.T[2] == 16) { STMG_T3K(16) }
+  else if (pl.T[2] == 4) { STMG_T3K(4) }
+  else fail(STMG_E_STATE, "fused transfer z chunk");
+#undef STMG_T3K
+#undef STMG_T3
+  STMG_CHECK_LAUNCH();
+}
+
+template void tensor3<double>(const double*, double*, int, const int*, const int*, const Tensor3Plan&,
+                              const T3Axis*, bool, hipStream_t);
+template void tensor3<float>(const float*, float*, int, const int*, const int*, const Tensor3Plan&,
+                             const T3Axis*, bool, hipStream_t);
 
 template <class T>
 void time_transfer(const T* P, int nf, int nc, long long nx, const unsigned char* mask, const T* in, T* out,

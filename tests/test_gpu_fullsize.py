@@ -6,9 +6,10 @@
 
 The assembled oracle does not fit at these sizes, so the operator and one smoother step are
 compared on sampled entries computed one by one by the oracle (cell-local assembly of the
-same definitions), and the V-cycle and the solve are checked through properties that hold
-at any size: linearity and contraction of the V-cycle, and the true residual of the solve
-(the GPU's own and the oracle's on sampled rows).
+same definitions), and so are the grid transfers of the first p- and h-level pairs; the
+V-cycle and the solve are checked through properties that hold at any size: linearity and
+contraction of the V-cycle, and the true residual of the solve (the GPU's own and the
+oracle's on sampled rows).
 """
 import numpy as np
 import pytest
@@ -87,6 +88,46 @@ def test_smoother_sampled_entries(setup):
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print(cfg.name, "smoother sampled max rel err", err, "omega", omega, flush=True)
     assert err < (1e-10 if vdt == torch.float64 else 2e-5)
+
+
+def test_transfer_sampled_entries(setup):
+    """Prolongation and restriction across the first p-level and the first h-level pair, on
+    sampled entries of the oracle's tensor-product transfers (FP64 workloads also in FP32)."""
+    cfg, h, smp, pts, vdt, kw = setup
+    spaces = smp.level_spaces()
+    assert h.info["n_levels"] == len(spaces)
+    pairs = [0] + [l for l in range(len(spaces) - 1) if spaces[l].cells != spaces[l + 1].cells][:1]
+    rng = np.random.default_rng(6)
+    for l in pairs:
+        fine, coarse = spaces[l], spaces[l + 1]
+        assert h.info["n_x"][l] == fine.n_x and h.info["n_x"][l + 1] == coarse.n_x
+        n_t = h.info["n_t_level"][l]
+        ptf = sampled.lattice_points(fine.p, fine.cells, n_t, 24, 4, seed=50 + l)
+        ptc = sampled.lattice_points(coarse.p, coarse.cells, n_t, 24, 4, seed=80 + l)
+        ec = rng.standard_normal((n_t, coarse.n_x))
+        ref_p = smp.prolong_entries(ec, l, ptf)
+        for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+            if dt == torch.float64 and vdt != torch.float64:
+                continue
+            f = torch.empty(h.size(l), dtype=dt, device=DEV)
+            h.prolongate(_dev(ec, dt), f, level=l)
+            err = np.abs(_entries(f, ptf, fine.n_x) - ref_p).max() / np.abs(ref_p).max()
+            del f
+            print(cfg.name, f"level {l} prolongation {dt} sampled max rel err", err, flush=True)
+            assert err < tol
+        del ec
+        rf = rng.standard_normal((n_t, fine.n_x))
+        ref_r = smp.restrict_entries(rf, l, ptc)
+        for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+            if dt == torch.float64 and vdt != torch.float64:
+                continue
+            c = torch.empty(h.size(l + 1), dtype=dt, device=DEV)
+            h.restrict(_dev(rf, dt), c, level=l)
+            err = np.abs(_entries(c, ptc, coarse.n_x) - ref_r).max() / np.abs(ref_r).max()
+            del c
+            print(cfg.name, f"level {l} restriction {dt} sampled max rel err", err, flush=True)
+            assert err < tol
+        del rf
 
 
 def test_vcycle_linear_and_contracting(setup):
