@@ -49,27 +49,28 @@ __device__ inline BrickPos brick_pos(const BrickLaunch& L, const GeomDesc& g) {
   return P;
 }
 
-// Rows (plane j, z, y) of the brick's node box: thread `tid` keeps its x position and walks the
-// rows r0, r0 + per, r0 + 2 per, ... with a carried (j, z, y) counter (no integer division in the
-// loop).  Rows come in batches so that every global load of a batch is issued before the first of
-// them is used.
-struct RowWalk {
-  int per, lx, ly, lz, j;
-  bool on;
-  __device__ RowWalk(int tid, int nthr, const int NBd[3]) {
-    per = nthr / NBd[0];
-    lx = tid % NBd[0];
-    const int r0 = tid / NBd[0];
-    on = r0 < per;
-    ly = r0 % NBd[1];
-    lz = (r0 / NBd[1]) % NBd[2];
-    j = r0 / (NBd[1] * NBd[2]);
-  }
-  __device__ void next(const int NBd[3]) {
-    ly += per;
-    while (ly >= NBd[1]) {
-      ly -= NBd[1];
-      if (++lz == NBd[2]) { lz = 0; ++j; }
+// Thread layout of the stage and write-back loops.  The brick's node box is a stack of
+// NBd[2] * n_t planes (lz, j) of NBd[0] x NBd[1] nodes.  A thread keeps one (lx, ly) position of a
+// plane (several when a plane has more nodes than the workgroup has threads) and walks the planes
+// lz = slot, slot + step, ... with a carried (lz, j) counter, so the x and y parts of every index and
+// predicate are formed once per thread and a plane step costs an add and a compare.  Planes come in
+// batches so that every global load of a batch is issued before the first of them is used.
+struct PlaneWalk {
+  int np;             // nodes per plane
+  int e0, estep;      // first position of this thread and the step between its positions
+  int slot, step;     // first lz and the lz step (step <= NBd[2])
+  __device__ PlaneWalk(int tid, int nthr, const int NBd[3]) {
+    np = NBd[0] * NBd[1];
+    if (np <= nthr) {
+      step = min(nthr / np, NBd[2]);
+      slot = tid / np;
+      e0 = slot < step ? tid - slot * np : np;    // threads past the last slot have no position
+      estep = np;
+    } else {
+      step = 1;
+      slot = 0;
+      e0 = tid;
+      estep = nthr;
     }
   }
 };
@@ -89,27 +90,36 @@ __device__ inline void wave_sync_lds() {
 template <class T>
 __device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
                                    const T* __restrict__ x, T* xs) {
-  const int nbx = L.NBd[0], nby = L.NBd[1];
+  const int nbx = L.NBd[0], nbz = L.NBd[2];
   const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
-  RowWalk w(threadIdx.x, blockDim.x, L.NBd);
-  while (w.on && w.j < n_t) {
-    T v[ROW_BATCH];
-    int dst[ROW_BATCH];
+  const long long nn01 = (long long)nn0 * nn1;
+  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  for (int e = w.e0; e < w.np; e += w.estep) {
+    const int ly = e / nbx, lx = e - ly * nbx;
+    const int gx = P.g0[0] + lx, gy = P.g0[1] + ly;
+    const bool inxy = gx > 0 && gx < nn0 - 1 && gy > 0 && gy < nn1 - 1;
+    const T* xp = x + (long long)gy * nn0 + gx;
+    T* sp = xs + e;
+    int lz = w.slot, j = 0;
+    while (j < n_t) {
+      T v[ROW_BATCH];
+      int dst[ROW_BATCH];
 #pragma unroll
-    for (int u = 0; u < ROW_BATCH; ++u) {
-      v[u] = 0;
-      dst[u] = -1;
-      if (w.j < n_t) {
-        const int gx = P.g0[0] + w.lx, gy = P.g0[1] + w.ly, gz = P.g0[2] + w.lz;
-        const bool in = gx > 0 && gx < nn0 - 1 && gy > 0 && gy < nn1 - 1 && gz > 0 && gz < nn2 - 1;
-        if (in) v[u] = x[(long long)w.j * g.nx + ((long long)gz * nn1 + gy) * nn0 + gx];
-        dst[u] = w.j * P.NB + (w.lz * nby + w.ly) * nbx + w.lx;
-        w.next(L.NBd);
+      for (int u = 0; u < ROW_BATCH; ++u) {
+        v[u] = 0;
+        dst[u] = -1;
+        if (j < n_t) {
+          const int gz = P.g0[2] + lz;
+          if (inxy && gz > 0 && gz < nn2 - 1) v[u] = xp[(long long)j * g.nx + gz * nn01];
+          dst[u] = j * P.NB + lz * w.np;
+          lz += w.step;
+          if (lz >= nbz) { lz -= nbz; ++j; }
+        }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < ROW_BATCH; ++u)
-      if (dst[u] >= 0) xs[dst[u]] = v[u];
+      for (int u = 0; u < ROW_BATCH; ++u)
+        if (dst[u] >= 0) sp[dst[u]] = v[u];
+    }
   }
 }
 
@@ -120,43 +130,55 @@ __device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, cons
 template <class T>
 __device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
                                    const T* xs, T scale, int overwrite, const T* __restrict__ base, T* y) {
-  const int nbx = L.NBd[0], nby = L.NBd[1];
+  const int nbx = L.NBd[0], nbz = L.NBd[2];
   const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
+  const long long nn01 = (long long)nn0 * nn1;
   const int p = g.p;
-  const int last[3] = {P.nc[0] * p, P.nc[1] * p, P.nc[2] * p};
-  RowWalk w(threadIdx.x, blockDim.x, L.NBd);
-  while (w.on && w.j < n_t) {
-    long long gi[ROW_BATCH];
-    int mode[ROW_BATCH];        // -1 skip, 0 boundary store, 1 store (base + v), 2 update
-    T old[ROW_BATCH], v[ROW_BATCH];
+  const int last0 = P.nc[0] * p, last1 = P.nc[1] * p, last2 = P.nc[2] * p;
+  // a node on a shared brick face is stored by the brick of the lowest colour holding it
+  const bool zlo_shared = P.b[2] > 0, zhi_shared = P.b[2] + 1 < L.nbt[2], zodd = (P.b[2] & 1) != 0;
+  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  for (int e = w.e0; e < w.np; e += w.estep) {
+    const int ly = e / nbx, lx = e - ly * nbx;
+    if (lx > last0 || ly > last1) continue;                     // outside the brick's cells
+    const int gx = P.g0[0] + lx, gy = P.g0[1] + ly;
+    const bool shx = (lx == 0 && P.b[0] > 0) || (lx == last0 && P.b[0] + 1 < L.nbt[0]);
+    const bool shy = (ly == 0 && P.b[1] > 0) || (ly == last1 && P.b[1] + 1 < L.nbt[1]);
+    const bool fxy = !(shx && (P.b[0] & 1)) && !(shy && (P.b[1] & 1));
+    const bool bxy = gx == 0 || gx == nn0 - 1 || gy == 0 || gy == nn1 - 1;
+    const long long oxy = (long long)gy * nn0 + gx;
+    const T* sp = xs + e;
+    int lz = w.slot, j = 0;
+    while (j < n_t) {
+      long long gi[ROW_BATCH];
+      int mode[ROW_BATCH];        // -1 skip, 0 boundary store, 1 store (base + v), 2 update
+      T old[ROW_BATCH], v[ROW_BATCH];
 #pragma unroll
-    for (int u = 0; u < ROW_BATCH; ++u) {
-      mode[u] = -1;
-      old[u] = 0;
-      v[u] = 0;
-      gi[u] = 0;
-      if (w.j < n_t) {
-        const int lx = w.lx, ly = w.ly, lz = w.lz;
-        if (lx <= last[0] && ly <= last[1] && lz <= last[2]) {      // inside the brick's cells
-          const int gx = P.g0[0] + lx, gy = P.g0[1] + ly, gz = P.g0[2] + lz;
-          const bool shx = (lx == 0 && P.b[0] > 0) || (lx == last[0] && P.b[0] + 1 < L.nbt[0]);
-          const bool shy = (ly == 0 && P.b[1] > 0) || (ly == last[1] && P.b[1] + 1 < L.nbt[1]);
-          const bool shz = (lz == 0 && P.b[2] > 0) || (lz == last[2] && P.b[2] + 1 < L.nbt[2]);
-          const bool first = !(shx && (P.b[0] & 1)) && !(shy && (P.b[1] & 1)) && !(shz && (P.b[2] & 1));
-          const bool bnd = gx == 0 || gx == nn0 - 1 || gy == 0 || gy == nn1 - 1 || gz == 0 || gz == nn2 - 1;
-          gi[u] = (long long)w.j * g.nx + ((long long)gz * nn1 + gy) * nn0 + gx;
-          const bool store = overwrite && first;
-          mode[u] = bnd ? (store ? 0 : -1) : (store ? 1 : 2);
-          if (mode[u] == 0 || mode[u] == 1) old[u] = base ? base[gi[u]] : (T)0;
-          else if (mode[u] == 2) old[u] = y[gi[u]];
-          if (mode[u] >= 1) v[u] = scale * xs[w.j * P.NB + (lz * nby + ly) * nbx + lx];
+      for (int u = 0; u < ROW_BATCH; ++u) {
+        mode[u] = -1;
+        old[u] = 0;
+        v[u] = 0;
+        gi[u] = 0;
+        if (j < n_t) {
+          if (lz <= last2) {
+            const int gz = P.g0[2] + lz;
+            const bool shz = (lz == 0 && zlo_shared) || (lz == last2 && zhi_shared);
+            const bool store = overwrite && fxy && !(shz && zodd);
+            const bool bnd = bxy || gz == 0 || gz == nn2 - 1;
+            gi[u] = (long long)j * g.nx + gz * nn01 + oxy;
+            mode[u] = bnd ? (store ? 0 : -1) : (store ? 1 : 2);
+            if (mode[u] == 0 || mode[u] == 1) old[u] = base ? base[gi[u]] : (T)0;
+            else if (mode[u] == 2) old[u] = y[gi[u]];
+            if (mode[u] >= 1) v[u] = scale * sp[j * P.NB + lz * w.np];
+          }
+          lz += w.step;
+          if (lz >= nbz) { lz -= nbz; ++j; }
         }
-        w.next(L.NBd);
       }
-    }
 #pragma unroll
-    for (int u = 0; u < ROW_BATCH; ++u)
-      if (mode[u] >= 0) y[gi[u]] = old[u] + v[u];
+      for (int u = 0; u < ROW_BATCH; ++u)
+        if (mode[u] >= 0) y[gi[u]] = old[u] + v[u];
+    }
   }
 }
 
