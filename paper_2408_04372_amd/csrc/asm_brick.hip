@@ -97,7 +97,7 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
   T* sL = sQ + 3 * 4 * NN;                            // [3][4][N]
   for (int e = tid; e < 3 * 4 * NN; e += nthr) sQ[e] = A.fq[e];
   for (int e = tid; e < 3 * 4 * N; e += nthr) sL[e] = A.fl[e];
-  brick_stage<T>(g, A.L, P, n_t, A.r, xs);
+  brick_stage<T, 24>(g, A.L, P, n_t, A.r, xs);
   __syncthreads();
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
     __syncthreads();
   }
 
-  brick_write<T>(g, A.L, P, n_t, xs, A.omega, A.overwrite, (const T*)nullptr, A.u);
+  brick_write<T, 24>(g, A.L, P, n_t, xs, A.omega, A.overwrite, (const T*)nullptr, A.u);
 }
 
 template <class T, int N, int NTC>

@@ -54,7 +54,8 @@ __device__ inline BrickPos brick_pos(const BrickLaunch& L, const GeomDesc& g) {
 // plane (several when a plane has more nodes than the workgroup has threads) and walks the planes
 // lz = slot, slot + step, ... with a carried (lz, j) counter, so the x and y parts of every index and
 // predicate are formed once per thread and a plane step costs an add and a compare.  Planes come in
-// batches so that every global load of a batch is issued before the first of them is used.
+// batches of ROW_BATCH so that every global load of a batch is issued before the first of them is
+// used (24 covers the 20 planes per thread of a Q4 brick one cell deep with four temporal DoFs).
 struct PlaneWalk {
   int np;             // nodes per plane
   int e0, estep;      // first position of this thread and the step between its positions
@@ -74,7 +75,6 @@ struct PlaneWalk {
     }
   }
 };
-constexpr int ROW_BATCH = 8;
 
 // Order LDS accesses of one wave: the LDS executes a wave's operations in issue order, so a value
 // written by one lane is visible to another lane of the same wave once the compiler keeps the
@@ -87,7 +87,7 @@ __device__ inline void wave_sync_lds() {
 
 // xs[j][node] = x on the brick's nodes for every temporal plane j < n_t (Dirichlet nodes and nodes
 // past the lattice read as zero).
-template <class T>
+template <class T, int ROW_BATCH>
 __device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
                                    const T* __restrict__ x, T* xs) {
   const int nbx = L.NBd[0], nbz = L.NBd[2];
@@ -127,7 +127,7 @@ __device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, cons
 //   overwrite: y = base + scale * xs by the brick of the lowest colour holding the node (base null:
 //              zero), y += scale * xs by the others; Dirichlet nodes receive base (or zero) only;
 //   otherwise: y += scale * xs on interior nodes.
-template <class T>
+template <class T, int ROW_BATCH>
 __device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
                                    const T* xs, T scale, int overwrite, const T* __restrict__ base, T* y) {
   const int nbx = L.NBd[0], nbz = L.NBd[2];
@@ -181,6 +181,7 @@ __device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, cons
     }
   }
 }
+
 
 struct BrickPlan {
   int B[3] = {1, 1, 1};

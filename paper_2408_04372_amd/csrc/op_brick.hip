@@ -59,6 +59,9 @@ struct BrickOpArgs {
 template <class T, int N>
 __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   constexpr int p = N - 1;
+  // global loads in flight per thread in the stage and write-back (measured on 128^3 Q4 and Q2
+  // levels: 24 for Q4, whose compute phase sets the register count anyway, 8 for lower degrees)
+  constexpr int OP_BATCH = N >= 5 ? 24 : 8;
   constexpr int TPW = 64 / N;           // teams per wave
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const GeomDesc& g = A.g;
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   for (int e = tid; e < nnnz; e += nthr) { nval_s[e] = A.tp.nval[e]; ncol_s[e] = A.tp.ncol[e]; }
   for (int e = tid; e <= n_t; e += nthr) { mptr_s[e] = A.tp.mptr[e]; nptr_s[e] = A.tp.nptr[e]; }
 
-  brick_stage<T>(g, A.L, P, n_t, A.x, xs);
+  brick_stage<T, OP_BATCH>(g, A.L, P, n_t, A.x, xs);
   __syncthreads();
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
     __syncthreads();
   }
 
-  brick_write<T>(g, A.L, P, n_t, xs, A.scale, A.overwrite, A.base, A.y);
+  brick_write<T, OP_BATCH>(g, A.L, P, n_t, xs, A.scale, A.overwrite, A.base, A.y);
 }
 
 template <class T, int N>
