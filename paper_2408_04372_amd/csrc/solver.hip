@@ -24,7 +24,7 @@ void ensure_workspace(stmg_handle* h, long long n, int m) {
   h->V.alloc(sizeof(double) * n * (m + 1));
   h->w.alloc(sizeof(double) * n);
   h->red.alloc(sizeof(double) * RED_BLOCKS * PS);
-  h->dots.alloc(sizeof(double) * (m + 2));
+  h->dots.alloc(sizeof(double) * (m + 4));
   if (need32) {
     h->Z32.alloc(sizeof(float) * n * m);
     h->tmp32a.alloc(sizeof(float) * n);
@@ -170,10 +170,12 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
         std::vector<double> hc(j + 1, 0.0);
         std::vector<double> w2;
         for (int pass = 0; pass < 2; ++pass) {
+          // dots[0..j] = V^T w, dots[j+1] = ||w||^2, then dots[j+2..j+3] = ||w'||^2 and the
+          // non-finite flag of the update: one read-back per pass
           multi_dot(V, n, j + 1, vn, n, dots, red, s, true);
-          std::vector<double> hv = download<double>(dots, j + 2, s);
-          multi_axpy_neg_norm(V, n, j + 1, dots, vn, n, dots, red, s);
-          w2 = download<double>(dots, 2, s);
+          multi_axpy_neg_norm(V, n, j + 1, dots, vn, n, dots + j + 2, red, s);
+          std::vector<double> hv = download<double>(dots, j + 4, s);
+          w2.assign(hv.begin() + j + 2, hv.begin() + j + 4);
           for (int i = 0; i <= j; ++i) hc[i] += hv[i];
           const double ww = hv[j + 1];
           if (!std::isfinite(ww) || w2[1] != 0.0) { bad = true; break; }
