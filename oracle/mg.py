@@ -14,6 +14,12 @@ Section 3 of the paper.  Readings where the paper is silent:
     principal submatrix of the assembled level operator, inverted densely; every
     Dirichlet DoF is its own 1x1 identity block.  One step is
     u <- u + omega * sum_T R_T^T S_TT^{-1} R_T (f - S u).
+  * vertex-patch smoother (Section 5, named there as the extension of the cell-wise
+    smoother that gives robustness in p): one block per interior vertex v of the
+    level, on the lattice nodes strictly inside the 2^d cells around v, times the
+    temporal DoFs of one time cell; exact (principal submatrix) or separable
+    (Kronecker product of the per-axis principal submatrices of the assembled 1D
+    matrices, with the mean coefficient of the patch).  Summed like the cell blocks.
   * omega (eq. relaxation): 2 / (lambda_max + lambda_min) from real parts of the
     Ritz values of 15 Arnoldi steps on ASM * S, clamped to (0, 1].  Optional
     alternative (omega_rule < 0): |omega_rule| / lambda_max.
@@ -228,6 +234,90 @@ def fdm_blocks(op: spacetime.SlabOperator):
     return out
 
 
+def vertex_patches(space: spatial.Space):
+    """(vertex, nodes) for every interior vertex of the cell lattice: vertex coordinates v with
+    1 <= v_a <= cells_a - 1, and the global indices of the lattice nodes strictly inside the 2^d
+    cells around v (p (v_a - 1) < g_a < p (v_a + 1) per axis, x fastest)."""
+    d, p = space.dim, space.p
+    N = space.nodes
+    ranges = [range(1, space.cells[a]) for a in range(d)]
+    out = []
+    for v in np.array(np.meshgrid(*ranges[::-1], indexing="ij")).reshape(d, -1).T[:, ::-1]:
+        axes = [np.arange(p * (v[a] - 1) + 1, p * (v[a] + 1)) for a in range(d)]
+        g = np.zeros(1, dtype=np.int64)
+        stride = 1
+        for a in range(d):
+            g = (g[None, :] + axes[a][:, None] * stride).ravel()
+            stride *= N[a]
+        out.append((tuple(int(x) for x in v), np.sort(g)))
+    return out
+
+
+def patch_blocks(op: spacetime.SlabOperator, S: sp.csr_matrix):
+    """Exact vertex-patch blocks: (indices, inverse of the principal submatrix) for every interior
+    vertex patch times every time cell."""
+    sl = op.slab
+    nc = sl.nt_cell
+    c = sl.n_t // nc
+    Nx = op.space.n_x
+    S = S.tocsr()
+    out = []
+    for _, nodes in vertex_patches(op.space):
+        for m in range(c):
+            idx = np.concatenate([(m * nc + i) * Nx + nodes for i in range(nc)])
+            out.append((idx, np.linalg.inv(S[idx][:, idx].toarray())))
+    return out
+
+
+def fdm_patch_blocks(op: spacetime.SlabOperator):
+    """Separable vertex-patch blocks (Cartesian levels): per axis the principal submatrix of the
+    assembled 1D matrices on the patch's 2p - 1 inner nodes, M~ = M_z (x) M_y (x) M_x,
+    A~ = rho_v (A_z (x) M_y (x) M_x + M_z (x) A_y (x) M_x + M_z (x) M_y (x) A_x) with rho_v the mean
+    finest coefficient over the patch's 2^d cells; block M_tau (x) A~ + Ntilde (x) M~.  With a
+    constant coefficient this is the exact patch block."""
+    space, sl = op.space, op.slab
+    one_d, coef = fdm_setup(space)
+    d, p, r = space.dim, space.p, space.ratio
+    nc = sl.nt_cell
+    c = sl.n_t // nc
+    Nx = space.n_x
+    out = []
+    for v, nodes in vertex_patches(space):
+        Ms, As = [], []
+        for a in range(d):
+            idx = np.arange(p * (v[a] - 1) + 1, p * (v[a] + 1))
+            Ms.append(one_d[a][0][np.ix_(idx, idx)])
+            As.append(one_d[a][1][np.ix_(idx, idx)])
+        box = tuple(slice((v[a] - 1) * r, (v[a] + 1) * r) for a in reversed(range(d)))
+        rho = float(np.mean(coef[box]))
+        if d == 2:
+            Mt = np.kron(Ms[1], Ms[0])
+            At = rho * (np.kron(As[1], Ms[0]) + np.kron(Ms[1], As[0]))
+        else:
+            Mt = np.kron(Ms[2], np.kron(Ms[1], Ms[0]))
+            At = rho * (np.kron(As[2], np.kron(Ms[1], Ms[0])) + np.kron(Ms[2], np.kron(As[1], Ms[0]))
+                        + np.kron(Ms[2], np.kron(Ms[1], As[0])))
+        inv = np.linalg.inv(np.kron(sl.M_tau, At) + np.kron(sl.N_tilde, Mt))
+        for m in range(c):
+            idx = np.concatenate([(m * nc + i) * Nx + nodes for i in range(nc)])
+            out.append((idx, inv))
+    return out
+
+
+def smoother_blocks(op: spacetime.SlabOperator, S: sp.csr_matrix, asm_variant: int):
+    """Blocks of the additive Schwarz smoother: 0 exact cell blocks, 1 separable cell blocks,
+    2 separable vertex patches, 3 exact vertex patches."""
+    if asm_variant == 0:
+        return asm_blocks(op, S)
+    if asm_variant == 1:
+        return fdm_blocks(op)
+    if asm_variant == 2:
+        return fdm_patch_blocks(op)
+    if asm_variant == 3:
+        return patch_blocks(op, S)
+    raise ValueError("asm_variant must be 0..3")
+
+
 def asm_apply(level: Level, r: np.ndarray) -> np.ndarray:
     """sum_T R_T^T S_TT^{-1} R_T r, plus the identity on Dirichlet DoFs."""
     r = r.ravel()
@@ -314,7 +404,7 @@ class Hierarchy:
             if i == 0:
                 lev.lu = spla.splu(lev.S.tocsc())
             else:
-                lev.blocks = fdm_blocks(op) if asm_variant == 1 else asm_blocks(op, lev.S)
+                lev.blocks = smoother_blocks(op, lev.S, asm_variant)
                 if pairs[i - 1][1] is not sl:
                     lev.Pt = temporal.prolongation(sl, pairs[i - 1][1])
                 else:

@@ -202,3 +202,96 @@ def test_omega_estimate_is_exact_on_tiny_levels(problem, method, k, c, perturb):
     assert mg.estimate_omega(lev, rule=0.0) == pytest.approx(min(max(w_bal, 1e-3), 1.0), rel=1e-10)
     assert mg.estimate_omega(lev, rule=-1.5) == pytest.approx(min(max(w_top, 1e-3), 1.0), rel=1e-10)
     assert w_top < 1.0          # the pin is not decided by the clamp
+
+
+# --------------------------------------------------------------------------- vertex patches
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 2)])
+@pytest.mark.parametrize("method,problem", [(0, 0), (1, 1)])
+def test_single_vertex_patch_is_exact(dim, p, method, problem):
+    # 2^d cells and one time cell: the only interior vertex's patch holds every interior DoF, so
+    # one additive Schwarz step with omega = 1 is the direct solve
+    cells = (2, 2, 2) if dim == 3 else (2, 2, 1)
+    cfg = Config(dim=dim, problem=problem, time_method=method, p=p, k=2, n_time_cells=1, n_cells=cells,
+                 tau=0.2, perturb=0.1, coef="lognormal", coef_sigma=1.0, seed=8)
+    op = _op(cfg)
+    S = op.matrix()
+    assert len(mg.vertex_patches(op.space)) == 1
+    lev = mg.Level(op=op, S=S, blocks=mg.patch_blocks(op, S))
+    b = random_slab_vector(cfg, 4)
+    u = mg.smooth(lev, b, np.zeros_like(b), 1, omega=1.0)
+    assert np.allclose(u, op.solve(b).ravel(), atol=1e-11)
+
+
+def test_vertex_patches_cover_interior_nodes():
+    # a node lies strictly inside the patch of vertex v along axis a for v_a = g_a / p when it sits
+    # on a cell face (g_a % p == 0), else for v_a in {c_a, c_a + 1} (c_a its cell); the patch count
+    # of a node is the product over the axes, restricted to interior vertices
+    cfg = Config(dim=3, p=2, k=0, n_time_cells=1, n_cells=(3, 4, 2), tau=0.1)
+    space = _op(cfg).space
+    count = np.zeros(space.n_x, dtype=int)
+    for v, nodes in mg.vertex_patches(space):
+        assert len(nodes) == (2 * space.p - 1) ** 3
+        count[nodes] += 1
+    N = space.nodes
+    for g in range(space.n_x):
+        c = [g % N[0], (g // N[0]) % N[1], g // (N[0] * N[1])]
+        if any(x == 0 or x == m - 1 for x, m in zip(c, N)):
+            assert count[g] == 0
+            continue
+        want = 1
+        for a in range(3):
+            if c[a] % space.p == 0:
+                want *= 1
+            else:
+                ca = c[a] // space.p
+                want *= sum(1 for v in (ca, ca + 1) if 1 <= v <= space.cells[a] - 1)
+        assert count[g] == want
+
+
+def test_separable_patches_exact_for_constant_coefficient():
+    # Cartesian mesh and constant coefficient: the patch operator is a Kronecker product of the
+    # assembled 1D patch matrices, so the separable patch block is the exact one
+    for cfg in [Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=2, n_cells=(3, 2, 4),
+                       tau=0.05, coef="one", seed=3),
+                Config(dim=2, problem=1, time_method=1, p=3, k=2, n_time_cells=2, n_cells=(3, 4, 1),
+                       tau=0.05, coef="one", seed=4)]:
+        verts, coef = draw_problem(cfg)
+        op = spacetime.from_config(cfg, verts, coef * 1.7)
+        exact = mg.patch_blocks(op, op.matrix())
+        fdm = mg.fdm_patch_blocks(op)
+        assert len(exact) == len(fdm) > 0
+        for (i1, b1), (i2, b2) in zip(exact, fdm):
+            assert np.array_equal(i1, i2)
+            assert np.allclose(b1, b2, rtol=1e-10, atol=1e-10 * np.abs(b1).max())
+
+
+def test_separable_patches_use_patch_mean_coefficient():
+    # scaling the coefficient of one cell of a 2^3 patch by s changes the patch's mean by (s - 1)/8
+    cfg = Config(dim=3, problem=0, time_method=0, p=2, k=0, n_time_cells=1, n_cells=(2, 2, 2), tau=1.0,
+                 coef="one", seed=5)
+    verts, coef = draw_problem(cfg)
+    c2 = coef.copy()
+    c2[5] = 9.0                     # rho_mean = (7 + 9) / 8 = 2
+    op1 = spacetime.from_config(cfg, verts, coef)
+    op2 = spacetime.from_config(cfg, verts, c2)
+    (i1, b1), = mg.fdm_patch_blocks(op1)
+    (i2, b2), = mg.fdm_patch_blocks(op2)
+    Mt = op1.Mi.toarray()[np.ix_(i1, i1)]
+    B1, B2 = np.linalg.inv(b1), np.linalg.inv(b2)
+    assert np.allclose(B2 - Mt, 2.0 * (B1 - Mt), rtol=1e-10, atol=1e-12)
+
+
+def test_vertex_patch_hierarchy_solves():
+    # V-cycle with exact and separable vertex patches as an FGMRES preconditioner reaches the
+    # direct solution (Alg. stmg with the patch smoother on every level)
+    cfg = Config(dim=3, problem=1, time_method=1, p=2, k=2, n_time_cells=2, n_cells=(4, 4, 4), tau=0.05,
+                 coef="lognormal", coef_sigma=0.5, seed=9)
+    op = _op(cfg)
+    b = random_slab_vector(cfg, 6)
+    xd = op.solve(b).ravel()
+    for av in (2, 3):
+        H = mg.Hierarchy(op, asm_variant=av, omega_rule=-1.5)
+        x, it, rr = krylov.fgmres(op.apply, b, H.vcycle, rtol=1e-11, restart=40, max_iter=200)
+        assert rr <= 1e-11 and it < 80
+        assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
