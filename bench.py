@@ -273,6 +273,34 @@ def solve_modes(h, b, x, precisions=(0, 1)):
     return res
 
 
+def smoother_variants(cfg, verts, coef, b, idx):
+    """FP64 time to 1e-8 with the cell-wise exact, cell-wise separable and separable vertex-patch
+    smoothers (asm_variant 0, 1, 2) on one workload: set-up, iterations, solve time and the
+    finest-level smoother time per application."""
+    import torch
+    from paper_2408_04372_amd import Handle
+    out = {}
+    for av, key in ((0, "cell_exact"), (1, "cell_separable"), (2, "vertex_patch_separable")):
+        kw = dict(LAUNCH[idx])
+        kw["asm_variant"] = av
+        t0 = time.time()
+        h = Handle(cfg, verts, coef, vcycle_dtypes=1, precision=0, rtol=1e-8, max_iter=400, omega=OMEGA, **kw)
+        setup = time.time() - t0
+        x = torch.zeros_like(b)
+        h.solve(b, x)
+        x.zero_()
+        h.kernel_stats(reset=True)
+        inf = h.solve(b, x)
+        ks = h.kernel_stats(reset=True)
+        out[key] = {"setup_s": setup, "iterations": inf["iterations"], "seconds": inf["seconds"],
+                    "rel_residual": inf["rel_residual"],
+                    "smoother_ms_per_application": 1e3 * ks["t_smoother"] / max(1, ks["n_smoother"])}
+        h.close()
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_config(idx, dev, learned_on, train_solves):
     """Time to 1e-8 (FP64 and FP32 V-cycle, learned stage on the 64^3 Q2 workload) and the
     operator / V-cycle rates of another single-GPU workload."""
@@ -290,10 +318,16 @@ def extra_config(idx, dev, learned_on, train_solves):
     nst = h.size(0)
     modes = solve_modes(h, b, x)
     out = {"workload": cfg.name, "n_st": nst, "setup_s": setup, "levels": h.info["n_levels"],
-           "device_GB": h.info["device_bytes"] / 1e9,
+           "device_GB": h.info["device_bytes"] / 1e9, "eig_resolves": h.info["eig_resolves"],
            "fp64": {k: modes[0][k] for k in ("iterations", "seconds", "rel_residual")},
            "fp32_vcycle": {k: modes[1][k] for k in ("iterations", "seconds", "rel_residual", "rel_diff_vs_fp64")}}
     out.update(rates(h, dev, nst))
+    if idx == 5:
+        h.close()
+        torch.cuda.empty_cache()
+        out["smoother_variants"] = smoother_variants(cfg, verts, coef, b, idx)
+        log(f"smoother variants ({cfg.name}): {json.dumps(out['smoother_variants'])}")
+        h = None
     if learned_on and idx == 5:
         # the learned stage: trained on seeded plain-multigrid solves (seeds 1001, 1002, ...) on a
         # 16^3-cell box of the same mesh width, degrees, time step and coefficient law, then
@@ -304,7 +338,8 @@ def extra_config(idx, dev, learned_on, train_solves):
         theta, ch, losses = learned.train_for_config(idx, solves=train_solves, epochs=2, lr=2e-3, cells=16,
                                                      log=log)
         t_train = time.time() - tl
-        h.close()
+        if h is not None:
+            h.close()
         torch.cuda.empty_cache()
         res = learned.gain(cfg, verts, coef, theta, ch, seeds=[3001, 3002, 3003], omega=OMEGA, rtol=1e-8,
                            max_iter=400, **LAUNCH[idx])
@@ -332,7 +367,7 @@ def extra_config(idx, dev, learned_on, train_solves):
                           "iterations": inftm["iterations"], "seconds": inftm["seconds"],
                           "rel_residual": inftm["rel_residual"]}
         htm.close()
-    else:
+    elif h is not None:
         h.close()
     del b, x
     torch.cuda.empty_cache()

@@ -35,7 +35,8 @@
  * stmg_restrict are asynchronous.  stmg_create and stmg_solve synchronise.
  *
  * Host-only queries (stmg_temporal_matrices, stmg_temporal_cell_factors,
- * stmg_temporal_prolongation, stmg_transfer_1d) need no handle and no device;
+ * stmg_temporal_dof_times, stmg_temporal_prolongation, stmg_transfer_1d) need no
+ * handle and no device;
  * they fill caller-owned host arrays with the set-up data the library builds.
  *
  * Errors: every function returns an stmg_status; nothing is thrown or aborted
@@ -112,7 +113,12 @@ typedef struct {
   uint64_t seed;           /* reserved for randomised setup steps */
   int32_t asm_variant;     /* 0: exact cell blocks, factored by generalised eigenvectors of the
                               probed principal submatrices; 1: separable surrogate (fast
-                              diagonalisation, Cartesian meshes only) */
+                              diagonalisation, Cartesian meshes only); 2: separable vertex
+                              patches (Section 5's extension of the cell-wise smoother: one block
+                              per interior vertex on the nodes strictly inside its 2^d cells,
+                              Kronecker product of the assembled 1D patch matrices with the
+                              patch-mean coefficient; Cartesian meshes with at least two cells
+                              per direction, at most 6 temporal DoFs per time cell) */
   int32_t time_mg;         /* 0: spatial levels only; 1: below the coarsest spatial level, coarsen in
                               time (Section 3.2): lower k by one per level to its minimum (dG 0,
                               cGP 1), then merge pairs of time cells while their number is even;
@@ -200,6 +206,14 @@ stmg_status stmg_smooth(stmg_handle* h, int level, int dtype, const void* b, voi
 /* z = V(r): one V-cycle of Alg. stmg on the finest level with zero initial
  * guess, nu1 = nu2 = n_smooth, exact coarsest-level solve.  r, z must not alias. */
 stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z);
+
+/* One iteration of the space-time multigrid method as a stationary solver (Alg. stmg applied
+ * to the current residual, Section 3.1): r = b - S x, z = V r (one V-cycle, the settings of
+ * stmg_vcycle), x <- x + z.  b, x, r, z: device vectors of level 0 in dtype, caller-owned,
+ * pairwise distinct (STMG_E_ARG otherwise); x is updated in place, r and z are outputs (the
+ * residual before the step and the correction).  dtype selects the hierarchy (FP64 or FP32)
+ * the residual and the V-cycle run in.  Asynchronous on the handle's stream. */
+stmg_status stmg_mg_step(stmg_handle* h, int dtype, const void* b, void* x, void* r, void* z);
 
 /* fine = P coarse: prolongation from level+1 to level (Section 3.2): the coarse
  * Q_p function evaluated at the fine nodes (P^h (x) I on every temporal plane),
@@ -355,6 +369,14 @@ stmg_status stmg_transfer_1d(int p_coarse, int n_coarse, int p_fine, int n_fine,
  * nt_cell x nt_cell, written when non-NULL (capacity cap doubles each). */
 stmg_status stmg_temporal_cell_factors(int problem, int method, int k, double tau, int64_t cap, int32_t* nt_cell,
                                        double* M_tau, double* N_tilde);
+
+/* Host only: the times of a slab's temporal DoFs (Sections 2.1 and 2.2): time cell m of
+ * length tau starts at t0 + m tau, and its DoFs sit at the k+1 right Radau points (dG) or at the
+ * last k of the k+1 Gauss-Lobatto points (cGP) of the cell.  Arguments and checks as for
+ * stmg_temporal_matrices; t0 must be finite.  n_t receives the number of DoFs; times (host,
+ * capacity cap doubles, DoF order of the slab vectors) is written when non-NULL. */
+stmg_status stmg_temporal_dof_times(int problem, int method, int k, int n_time_cells, double tau, double t0,
+                                    int64_t cap, int32_t* n_t, double* times);
 
 /* Host only: the temporal prolongation between two discretisations of one slab
  * of length slab_length (Section 3.2: the coarse trial functions evaluated at

@@ -125,6 +125,11 @@ _SIGS = {
     "stmg_transfer_1d": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
                          ctypes.c_int),
+    "stmg_temporal_dof_times": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
+                                ctypes.c_int),
+    "stmg_mg_step": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                     ctypes.c_int),
     "stmg_temporal_prolongation": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p], ctypes.c_int),
@@ -179,6 +184,18 @@ def temporal_cell_factors(problem: int, method: int, k: int, tau: float):
     _check(lib.stmg_temporal_cell_factors(problem, method, k, tau, n.value * n.value, ctypes.byref(n),
                                           *[ctypes.c_void_p(a.ctypes.data) for a in out]))
     return tuple(out)
+
+
+def temporal_dof_times(problem: int, method: int, k: int, n_time_cells: int, tau: float, t0: float = 0.0):
+    """Times of a slab's temporal DoFs as the library places them (host only; numpy array)."""
+    import numpy as np
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.stmg_temporal_dof_times(problem, method, k, n_time_cells, tau, t0, 0, ctypes.byref(n), None))
+    out = np.empty(n.value)
+    _check(lib.stmg_temporal_dof_times(problem, method, k, n_time_cells, tau, t0, n.value, ctypes.byref(n),
+                                       ctypes.c_void_p(out.ctypes.data)))
+    return out
 
 
 def transfer_1d(p_coarse: int, n_coarse: int, p_fine: int, n_fine: int):
@@ -319,6 +336,14 @@ class Handle:
         d = _dtype_code(r)
         _check(self.lib.stmg_vcycle(self.h, d, _ptr(r, r.dtype), _ptr(z, r.dtype)))
         return z
+
+    def mg_step(self, b, x, r, z):
+        """x <- x + V(b - S x) on the finest level; r, z receive the residual and the correction."""
+        for t in (b, x, r, z):
+            self._sz(t, 0)
+        d = _dtype_code(x)
+        _check(self.lib.stmg_mg_step(self.h, d, _ptr(b, x.dtype), _ptr(x, x.dtype), _ptr(r, x.dtype), _ptr(z, x.dtype)))
+        return x
 
     def prolongate(self, coarse, fine, level: int = 0):
         self._sz(coarse, level + 1); self._sz(fine, level)

@@ -55,7 +55,7 @@ void check_config(const stmg_config* c) {
   if (c->precision < 0 || c->precision > 2) fail(STMG_E_ARG, "precision must be 0, 1 or 2");
   if (c->restart < 1 || c->restart > 200) fail(STMG_E_ARG, "restart must be in 1..200");
   if (c->gram_schmidt != 0 && c->gram_schmidt != 1) fail(STMG_E_ARG, "gram_schmidt must be 0 or 1");
-  if (c->asm_variant != 0 && c->asm_variant != 1) fail(STMG_E_ARG, "asm_variant must be 0 or 1");
+  if (c->asm_variant < 0 || c->asm_variant > 2) fail(STMG_E_ARG, "asm_variant must be 0, 1 or 2");
   if (c->time_mg != 0 && c->time_mg != 1) fail(STMG_E_ARG, "time_mg must be 0 or 1");
   if (c->kernel_path < STMG_PATH_DEFAULT || c->kernel_path > STMG_PATH_COLOUR)
     fail(STMG_E_ARG, "kernel_path must be 0, 1 or 2");
@@ -141,6 +141,8 @@ stmg_status stmg_create(const stmg_config* cfg, const double* vertices, const do
     if (vertices) check_vertices(cfg, vertices);
     if (vertices && cfg->asm_variant == 1)
       stmg::fail(STMG_E_UNSUPPORTED, "the separable smoother (asm_variant 1) needs a Cartesian mesh");
+    if (vertices && cfg->asm_variant == 2)
+      stmg::fail(STMG_E_UNSUPPORTED, "the vertex-patch smoother (asm_variant 2) needs a Cartesian mesh");
     auto t0 = std::chrono::steady_clock::now();
     int64_t bytes0 = stmg::DevBuf::total_bytes();
     std::unique_ptr<stmg_handle> h(new stmg_handle());
@@ -205,6 +207,21 @@ stmg_status stmg_vcycle(stmg_handle* h, int dtype, const void* r, void* z) {
     if (r == z) stmg::fail(STMG_E_ARG, "r and z must not alias");
     if (dtype == STMG_F64) stmg::vcycle<double>(h, 0, (const double*)r, (double*)z);
     else stmg::vcycle<float>(h, 0, (const float*)r, (float*)z);
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_mg_step(stmg_handle* h, int dtype, const void* b, void* x, void* r, void* z) {
+  return guarded([&]() -> stmg_status {
+    level_of(h, 0);
+    check_dtype(h, dtype, true, 0);
+    if (!b || !x || !r || !z) stmg::fail(STMG_E_ARG, "b, x, r or z is NULL");
+    const void* v[4] = {b, x, r, z};
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (v[i] == v[j]) stmg::fail(STMG_E_ARG, "b, x, r and z must not alias");
+    if (dtype == STMG_F64) stmg::mg_step<double>(h, (const double*)b, (double*)x, (double*)r, (double*)z);
+    else stmg::mg_step<float>(h, (const float*)b, (float*)x, (float*)r, (float*)z);
     return STMG_OK;
   });
 }
@@ -465,6 +482,24 @@ stmg_status stmg_temporal_cell_factors(int problem, int method, int k, double ta
       if (!dst[m]) continue;
       if (cap < (int64_t)T.nt_cell * T.nt_cell) stmg::fail(STMG_E_ARG, "cap is smaller than nt_cell * nt_cell");
       std::copy(src[m]->a.begin(), src[m]->a.end(), dst[m]);
+    }
+    return STMG_OK;
+  });
+}
+
+stmg_status stmg_temporal_dof_times(int problem, int method, int k, int n_time_cells, double tau, double t0,
+                                    int64_t cap, int32_t* n_t, double* times) {
+  return guarded([&] {
+    check_temporal(problem, method, k, n_time_cells, tau);
+    if (!n_t) stmg::fail(STMG_E_ARG, "n_t is NULL");
+    if (!std::isfinite(t0)) stmg::fail(STMG_E_ARG, "t0 must be finite");
+    const stmg::hm::Temporal T = stmg::hm::temporal(problem, method, k, n_time_cells, tau);
+    *n_t = T.n_t;
+    if (times) {
+      if (cap < (int64_t)T.n_t) stmg::fail(STMG_E_ARG, "cap is smaller than n_t");
+      const stmg::hm::Vec pos = stmg::hm::dof_positions(T);
+      for (int m = 0; m < n_time_cells; ++m)
+        for (int l = 0; l < T.nt_cell; ++l) times[m * T.nt_cell + l] = t0 + (m + pos[l]) * tau;
     }
     return STMG_OK;
   });

@@ -72,6 +72,7 @@ struct Level {
   LevelData<float> d32;
   bool has64 = false, has32 = false;
   std::vector<double> rho_mean;   // cell mean of the finest coefficient (separable smoother)
+  std::vector<double> rho_patch;  // vertex-patch mean of the finest coefficient (patch smoother)
   const TSet* ts = nullptr;       // temporal discretisation of this level
   int tkind = 0;                  // transfer to the next coarser level: 0 in space, 1 in time
   DevBuf Pt64, Pt32;              // temporal prolongation (n_t of this level x n_t of the next)
@@ -143,6 +144,7 @@ void noalloc_init(int device);
 template <class T> void vmult_noalloc(stmg_handle* h, int level, const T* x, T* y);
 template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int steps);
 template <class T> void vcycle(stmg_handle* h, int level, const T* f, T* u);
+template <class T> void mg_step(stmg_handle* h, const T* b, T* x, T* r, T* z);
 template <class T> void prolongate(stmg_handle* h, int level, const T* coarse, T* fine, bool accumulate);
 template <class T> void restrict_(stmg_handle* h, int level, const T* fine, T* coarse);
 void estimate_omegas(stmg_handle* h);

@@ -425,6 +425,49 @@ void setup_fdm(stmg_handle* h, Level& L) {
   if (L.has32) upload_fdm<float>(L.d32, q, lam, L.rho_mean, tmat, s);
 }
 
+// Vertex-patch smoother: per axis the assembled 1D matrices of two cells restricted to their
+// 2p - 1 inner nodes, with generalised eigenpairs A Q = M Q diag(lambda), Q^T M Q = I.
+void setup_patch(stmg_handle* h, Level& L) {
+  hipStream_t s = h->stream;
+  const int n = L.g.n, p = L.g.p, dim = L.g.dim, P = 2 * p - 1;
+  hm::Vec xq, wq;
+  hm::gauss(n, xq, wq);
+  hm::Mat V, D;
+  hm::lagrange(hm::gauss_lobatto(n), xq, V, D);
+  std::vector<double> q((size_t)3 * P * P, 0.0), lam((size_t)3 * P, 0.0);
+  for (int a = 0; a < dim; ++a) {
+    const double hx = (h->cfg.hi[a] - h->cfg.lo[a]) / L.cells[a];
+    hm::Mat M2(2 * p + 1, 2 * p + 1), A2(2 * p + 1, 2 * p + 1);
+    for (int e = 0; e < 2; ++e)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double m = 0.0, k = 0.0;
+          for (int t = 0; t < n; ++t) {
+            m += wq[t] * V(t, i) * V(t, j);
+            k += wq[t] * D(t, i) * D(t, j);
+          }
+          M2(e * p + i, e * p + j) += hx * m;
+          A2(e * p + i, e * p + j) += k / hx;
+        }
+    hm::Mat M1(P, P), A1(P, P);
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j) {
+        M1(i, j) = M2(i + 1, j + 1);
+        A1(i, j) = A2(i + 1, j + 1);
+      }
+    hm::Mat Q;
+    hm::Vec lm;
+    hm::sym_gen_eig(A1, M1, Q, lm);
+    for (int r = 0; r < P; ++r)
+      for (int c = 0; c < P; ++c) q[((size_t)a * P + r) * P + c] = Q(r, c);
+    for (int c = 0; c < P; ++c) lam[(size_t)a * P + c] = lm[c];
+  }
+  std::vector<double> tmat(L.ts->tm.M_tau.a);
+  tmat.insert(tmat.end(), L.ts->tm.N_tilde.a.begin(), L.ts->tm.N_tilde.a.end());
+  if (L.has64) upload_fdm<double>(L.d64, q, lam, L.rho_patch, tmat, s);
+  if (L.has32) upload_fdm<float>(L.d32, q, lam, L.rho_patch, tmat, s);
+}
+
 namespace {
 
 // Check of the generalised eigenpairs of a batch of cells (column-major ns x ns blocks):
@@ -470,6 +513,12 @@ constexpr double EIG_CHECK_TOL = 1e-8;
 void setup_smoother(stmg_handle* h, Level& L) {
   if (h->cfg.asm_variant == 1) {
     setup_fdm(h, L);
+    return;
+  }
+  if (h->cfg.asm_variant == 2) {
+    if (!patch_applicable(L.g, L.ts->tm.nt_cell))
+      fail(STMG_E_UNSUPPORTED, "the vertex-patch smoother needs Cartesian levels with at least two cells per direction");
+    setup_patch(h, L);
     return;
   }
   hipStream_t s = h->stream;
@@ -807,6 +856,30 @@ void build_hierarchy(stmg_handle* h, const double* vertices, const double* coeff
         L->rho_mean[c] = sum / cnt;
       }
     }
+    if (cfg.asm_variant == 2) {
+      // vertex-patch mean of the finest coefficient: the 2 ratio finest cells per axis around
+      // each interior vertex
+      const int r = L->ratio, rz = dim == 3 ? r : 1;
+      const int nv[3] = {L->cells[0] - 1, L->cells[1] - 1, dim == 3 ? L->cells[2] - 1 : 1};
+      if (nv[0] >= 1 && nv[1] >= 1 && nv[2] >= 1) {
+        L->rho_patch.assign((size_t)nv[0] * nv[1] * nv[2], 0.0);
+        for (int vz = 0; vz < nv[2]; ++vz)
+          for (int vy = 0; vy < nv[1]; ++vy)
+            for (int vx = 0; vx < nv[0]; ++vx) {
+              double sum = 0.0;
+              int cnt = 0;
+              for (int z = 0; z < 2 * rz; ++z)
+                for (int y = 0; y < 2 * r; ++y)
+                  for (int x = 0; x < 2 * r; ++x) {
+                    const long long fz = dim == 3 ? (long long)vz * r + z : 0;
+                    const long long f = (fz * fine_cells[1] + ((long long)vy * r + y)) * fine_cells[0] + ((long long)vx * r + x);
+                    sum += coef[f];
+                    ++cnt;
+                  }
+              L->rho_patch[((size_t)vz * nv[1] + vy) * nv[0] + vx] = sum / cnt;
+            }
+      }
+    }
     boundary_lists(*L, s);
     L->has64 = h->want64;
     L->has32 = h->want32;
@@ -891,7 +964,7 @@ template <class T> static void residual(stmg_handle* h, Level& L, const T* f, co
 // u += omega * ASM(r); u_zero: u is zero on entry (not read on the per-cell buffer path)
 template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T* u, bool u_zero = false) {
   LevelData<T>& d = ldata<T>(L);
-  T* cb = d.cellbuf.template as<T>();
+  T* cb = h->cfg.asm_variant == 2 ? nullptr : d.cellbuf.template as<T>();   // patches add into u
   const bool u_zero_in = u_zero;       // the brick smoother writes u itself
   const bool brick_fdm = h->cfg.asm_variant == 1 && L.brick && fdm_brick_applicable(L.g, L.ts->tm.nt_cell);
   if (u_zero && !cb && !brick_fdm) fill<T>(u, (T)0, L.nst(L.n_t()), h->stream);
@@ -903,6 +976,9 @@ template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T*
     asm_apply_fdm_brick<T>(L.g, L.n_t(), L.ts->tm.nt_cell, L.ts->tm.M_tau.a.data(), L.ts->tm.N_tilde.a.data(),
                            d.fq.template as<T>(), d.fl.template as<T>(), d.frho.template as<T>(), r, u,
                            (T)L.omega, u_zero_in, h->stream);
+  else if (h->cfg.asm_variant == 2)
+    asm_apply_patch<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
+                       d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream);
   else if (h->cfg.asm_variant == 1)
     asm_apply_fdm<T>(L.g, L.n_t(), L.ts->tm.nt_cell, d.fq.template as<T>(), d.fl.template as<T>(),
                      d.frho.template as<T>(), d.ftm.template as<T>(), r, u, (T)L.omega, h->stream, cb,
@@ -923,6 +999,17 @@ template <class T> void smooth(stmg_handle* h, int level, const T* b, T* x, int 
     asm_step<T>(h, L, d.r.template as<T>(), x);
   }
 }
+
+// One iteration of the multigrid method as a stationary solver on the finest level:
+// r = b - S x, z = V r, x <- x + z.
+template <class T> void mg_step(stmg_handle* h, const T* b, T* x, T* r, T* z) {
+  Level& L = *h->levels[0];
+  residual<T>(h, L, b, x, r);
+  vcycle<T>(h, 0, r, z);
+  axpby<T>((T)1, z, (T)1, x, (long long)L.n_t() * L.g.nx, h->stream);
+}
+template void mg_step<double>(stmg_handle*, const double*, double*, double*, double*);
+template void mg_step<float>(stmg_handle*, const float*, float*, float*, float*);
 
 template <class T> std::array<T3Axis, 3> fused_axes(const Fused3& F) {
   std::array<T3Axis, 3> a;

@@ -315,7 +315,6 @@ Temporal temporal(int problem, int method, int k, int c, double tau) {
   return T;
 }
 
-namespace {
 // local DoF positions in [0, 1] of one time cell: dG the k+1 right Radau nodes, cGP the last
 // k of the k+1 Gauss-Lobatto nodes
 Vec dof_positions(const Temporal& t) {
@@ -323,7 +322,6 @@ Vec dof_positions(const Temporal& t) {
   Vec gl = gauss_lobatto(t.k + 1);
   return Vec(gl.begin() + 1, gl.end());
 }
-}  // namespace
 
 Mat temporal_prolongation(const Temporal& fine, const Temporal& coarse) {
   if (fine.method != coarse.method) fail(STMG_E_ARG, "temporal transfer between different methods");

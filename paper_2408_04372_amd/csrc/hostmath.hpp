@@ -45,6 +45,9 @@ struct Temporal {
 };
 // problem: 0 heat, 1 wave; method: 0 dG, 1 cGP.
 Temporal temporal(int problem, int method, int k, int c, double tau);
+// Positions in [0, 1] of the temporal DoFs of one time cell (dG: the k+1 right Radau nodes; cGP:
+// the last k of the k+1 Gauss-Lobatto nodes).
+Vec dof_positions(const Temporal& t);
 // Temporal prolongation (fine.n_t x coarse.n_t) between two discretisations of the same slab
 // whose coarse trial space lies in the fine one: entry (i, j) is coarse trial function j at
 // the time of fine DoF i.  cGP: the first Gauss-Lobatto node of coarse cell M is the last DoF

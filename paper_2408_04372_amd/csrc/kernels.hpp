@@ -164,6 +164,16 @@ void asm_apply_fdm_brick(const GeomDesc& g, int n_t, int nt_cell, const double* 
                          const T* fq, const T* fl, const T* frho, const T* r, T* u, T omega, bool u_zero,
                          hipStream_t s);
 
+// Separable vertex-patch smoother (asm_patch.hip): u += omega * sum over interior vertices v and
+// time cells of the patch block solve (2p - 1 inner nodes per axis); pq: per axis the 1D
+// eigenvectors (P x P, row-major, Q(r, c) at r P + c), pl: their eigenvalues (P per axis), prho: the
+// mean coefficient per interior vertex ((nc_x - 1)(nc_y - 1)(nc_z - 1), x fastest), ptm: M_tau then
+// N~ (nt_cell x nt_cell each).  patch_applicable: Cartesian, at least two cells per direction.
+bool patch_applicable(const GeomDesc& g, int nt_cell);
+template <class T>
+void asm_apply_patch(const GeomDesc& g, int n_t, int nt_cell, const T* pq, const T* pl, const T* prho, const T* ptm,
+                     const T* r, T* u, T omega, hipStream_t s);
+
 // ---- smoother set-up check (hierarchy.hip) ----------------------------------------------------
 // flag[c] = 1 unless cell c's eigenpairs pass: max|R - I| <= tol for R = Q^T M Q, and per column k
 // max|AQ(:, k) - lambda_k T(:, k)| <= tol (max|AQ(:, k)| + |lambda_k| max|T(:, k)|) for T = M Q

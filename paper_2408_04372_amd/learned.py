@@ -58,15 +58,13 @@ def make_pairs(h, cfg, seeds, iters=(0, 1, 2, 3), log=None):
         xs = torch.zeros_like(b)
         h.solve(b, xs, raise_on_noconv=False)
         x = torch.zeros_like(b)
-        r = torch.empty_like(b)
         z = torch.empty_like(b)
         for k in range(max(iters) + 1):
-            h.vmult(x, r)
-            r = b - r
+            e = xs - x                      # training target e_k (data preparation, not the method)
+            r = torch.empty_like(b)
+            h.mg_step(b, x, r, z)           # r_k = b - S x_k, x_{k+1} = x_k + V r_k (library kernels)
             if k in iters:
-                pairs.append((r.clone(), (xs - x).clone()))
-            h.vcycle(r, z)
-            x = x + z
+                pairs.append((r, e))
     torch.cuda.synchronize()
     return pairs
 

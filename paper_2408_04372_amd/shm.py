@@ -29,7 +29,7 @@ def run(cfg, T: float, precision: int = 1, rtol: float = 1e-8, max_slabs: int = 
         sys.path.insert(0, ROOT)
     import torch
     import stmg_inputs as si
-    from paper_2408_04372_amd import Handle
+    from paper_2408_04372_amd import Handle, _lib
     verts, coef = si.draw_problem(cfg)
     h = Handle(cfg, verts, coef, precision=precision, rtol=rtol, omega=-1.5,
                vcycle_dtypes=2 if precision == 1 else 3, **kw)
@@ -41,9 +41,6 @@ def run(cfg, T: float, precision: int = 1, rtol: float = 1e-8, max_slabs: int = 
     b = torch.empty(n_t * nx, dtype=torch.float64, device=dev)
     U = torch.zeros_like(b)
     V = torch.empty_like(b)
-    # temporal DoF positions inside one time cell (cGP: the last k of the k+1 Gauss-Lobatto points)
-    inner = np.polynomial.legendre.Legendre.basis(cfg.k).deriv().roots() if cfg.k > 1 else np.array([])
-    loc = np.concatenate([np.sort((np.real(inner) + 1) / 2), [1.0]])
     slab_len = cfg.n_time_cells * cfg.tau
     n_slabs = min(int(round(T / slab_len)), max_slabs)
     times, values, infos = [], [], []
@@ -55,10 +52,11 @@ def run(cfg, T: float, precision: int = 1, rtol: float = 1e-8, max_slabs: int = 
         info = h.solve(b, U, raise_on_noconv=True)
         h.wave_velocity(U, V, u0, v0)
         vals = h.point_values(U, si.SHM_POINTS)          # (n_t, 3)
-        for m in range(cfg.n_time_cells):
-            for j in range(cfg.k):
-                times.append(t0 + (m + loc[j]) * cfg.tau)
-                values.append(vals[m * cfg.k + j].tolist())
+        # the library's temporal DoF times of this slab (cGP: the last k Gauss-Lobatto points per cell)
+        slab_times = _lib.temporal_dof_times(cfg.problem, cfg.time_method, cfg.k, cfg.n_time_cells, cfg.tau, t0)
+        for i in range(n_t):
+            times.append(float(slab_times[i]))
+            values.append(vals[i].tolist())
         u0 = U.view(n_t, nx)[-1].clone()
         v0 = V.view(n_t, nx)[-1].clone()
         infos.append({"slab": sl, "iterations": info["iterations"], "seconds": info["seconds"],

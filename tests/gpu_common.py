@@ -41,11 +41,15 @@ CASES = {
     "wave3d_q3_cgp2_brick": si.Config(dim=3, problem=1, time_method=1, p=3, k=2, n_time_cells=2,
                                       n_cells=(4, 5, 3), tau=0.02, hi=(1.0, 1.3, 0.9),
                                       coef="lognormal_checker", coef_sigma=1.0, seed=31),
-    # long in x: the pencils of the brick kernels are cut into several segments along x
+    # long in x: many bricks along x
     "heat3d_q2_dg1_long": si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=1,
                                     n_cells=(44, 3, 2), tau=0.01, hi=(4.0, 0.3, 0.2), coef="lognormal",
                                     coef_sigma=0.7, seed=32),
 }
+
+# Cartesian cases with at least two cells per direction (vertex-patch smoother)
+PATCH_CASES = ["heat2d_q2_dg1", "wave2d_q3_dg2", "heat3d_q1_dg0", "wave3d_q3_cgp2_c4", "heat3d_q4_dg1_brick",
+               "heat3d_q2_dg1_c4_brick"]
 
 # Cartesian 3D cases whose operator runs on the brick kernel by default
 BRICK_CASES = ["heat3d_q4_dg1_brick", "heat3d_q2_dg1_c4_brick", "wave3d_q3_cgp2_brick", "heat3d_q1_dg0",

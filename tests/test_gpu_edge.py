@@ -102,6 +102,11 @@ def test_level_arguments_rejected():
         assert h.lib.stmg_smooth(h.h, L - 1, 0, p(buf), p(out), 1) == 1  # coarsest level
         assert h.lib.stmg_prolongate(h.h, L - 1, 0, p(buf), p(out)) == 1
         assert h.lib.stmg_restrict(h.h, L - 1, 0, p(buf), p(out)) == 1
+        r = torch.zeros_like(buf)
+        z = torch.zeros_like(buf)
+        assert h.lib.stmg_mg_step(h.h, 0, p(buf), p(out), p(out), p(z)) == 1     # r aliases x
+        assert h.lib.stmg_mg_step(h.h, 0, p(buf), p(out), p(r), None) == 1       # NULL z
+        assert h.lib.stmg_mg_step(h.h, 2, p(buf), p(out), p(r), p(z)) == 1       # dtype
         assert len(h.lib.stmg_last_error()) > 0
         # the handle stays usable after rejected calls
         h.vmult(buf, out)

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import stmg_inputs as si
 from oracle import krylov, mg, spacetime
-from tests.gpu_common import BRICK_CASES, CASES, oracle_op, problem, rel_err
+from tests.gpu_common import BRICK_CASES, CASES, PATCH_CASES, oracle_op, problem, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -120,6 +120,35 @@ def test_vcycle(name):
             z = torch.empty(r.size, dtype=dt, device=DEV)
             h.vcycle(_t(r, dt), z)
             assert rel_err(_np(z), ref) < tol, dt
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q2_dg1_pert", "wave3d_q3_cgp2"])
+def test_mg_step(name):
+    """Two stationary multigrid iterations x <- x + V(b - S x) (Alg. stmg on the residual) against
+    the oracle's residual and V-cycle, with the residual and correction of each step."""
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    S = op.matrix()
+    H = mg.Hierarchy(op, n_smooth=cfg.n_smooth)
+    b = si.random_slab_vector(cfg, 21).ravel()
+    with _handle(cfg, verts, coef, omega=0.5) as h:
+        L = h.info["n_levels"]
+        for l in range(L - 1):
+            h.set_omega(l, H.levels[L - 1 - l].omega)
+        for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+            x_ref = np.zeros(b.size)
+            bt = _t(b, dt)
+            x = torch.zeros_like(bt)
+            r = torch.empty_like(bt)
+            z = torch.empty_like(bt)
+            for _ in range(2):
+                r_ref = b - S @ x_ref
+                z_ref = H.vcycle(r_ref)
+                x_ref = x_ref + z_ref
+                h.mg_step(bt, x, r, z)
+                assert rel_err(_np(r), r_ref) < tol, dt
+                assert rel_err(_np(z), z_ref) < tol, dt
+                assert rel_err(_np(x), x_ref) < tol, dt
 
 
 @pytest.mark.parametrize("rule", [0.0, -1.0])
@@ -251,6 +280,67 @@ def test_vcycle_and_solve_separable(name):
     print(name, info, "error", err)
     assert info["rel_residual"] <= 1e-12
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("name", PATCH_CASES)
+def test_smoother_vertex_patch(name):
+    """Two steps of the separable vertex-patch smoother against the oracle's patch blocks."""
+    cfg, verts, coef = problem(name)
+    print(f"case {name}", flush=True)
+    op = oracle_op(cfg, verts, coef)
+    lev = mg.Level(op=op, S=op.matrix())
+    lev.blocks = mg.fdm_patch_blocks(op)
+    rng = np.random.default_rng(18)
+    b = rng.standard_normal(lev.S.shape[0])
+    x0 = rng.standard_normal(lev.S.shape[0])
+    omega = 0.29
+    ref = mg.smooth(lev, b, x0, 2, omega=omega)
+    with _handle(cfg, verts, coef, omega=omega, asm_variant=2) as h:
+        for dt, tol in ((torch.float64, 1e-11), (torch.float32, 2e-4)):
+            x = _t(x0, dt)
+            h.smooth(_t(b, dt), x, steps=2, level=0)
+            err = rel_err(_np(x), ref)
+            print(dt, "vertex-patch smoother rel err", err)
+            assert err < tol, dt
+
+
+@pytest.mark.parametrize("name", ["heat2d_q2_dg1", "heat3d_q1_dg0", "heat3d_q4_dg1_brick"])
+def test_vcycle_and_solve_vertex_patch(name):
+    cfg, verts, coef = problem(name)
+    op = oracle_op(cfg, verts, coef)
+    H = mg.Hierarchy(op, n_smooth=cfg.n_smooth, asm_variant=2, omega_rule=-1.0)
+    rng = np.random.default_rng(19)
+    r = rng.standard_normal(op.matrix().shape[0])
+    ref = H.vcycle(r)
+    b = si.random_slab_vector(cfg, 20)
+    xd = op.solve(b)
+    with _handle(cfg, verts, coef, omega=-1.0, asm_variant=2, rtol=1e-12, precision=0, max_iter=300) as h:
+        L = h.info["n_levels"]
+        got_omega = h.info["omega"][: L - 1]
+        assert np.allclose(got_omega, [H.levels[L - 1 - l].omega for l in range(L - 1)], rtol=1e-4)
+        for l in range(L - 1):
+            h.set_omega(l, H.levels[L - 1 - l].omega)
+        for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-4)):
+            z = torch.empty(r.size, dtype=dt, device=DEV)
+            h.vcycle(_t(r, dt), z)
+            assert rel_err(_np(z), ref) < tol, dt
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        info = h.solve(_t(b).view(-1), x)
+        err = np.linalg.norm(_np(x) - xd.ravel()) / np.linalg.norm(xd)
+    print(name, info, "error", err)
+    assert info["rel_residual"] <= 1e-12
+    assert err < 1e-10
+
+
+def test_vertex_patch_rejects_unsupported_meshes():
+    from paper_2408_04372_amd import StmgError
+    cfg, verts, coef = problem("heat3d_q2_dg1_pert")
+    with pytest.raises(StmgError):
+        _handle(cfg, verts, coef, asm_variant=2)
+    cfg = si.Config(dim=3, problem=0, time_method=0, p=2, k=1, n_time_cells=1, n_cells=(3, 1, 2), tau=0.1, seed=3)
+    verts, coef = si.draw_problem(cfg)
+    with pytest.raises(StmgError):                 # one cell along y: no interior vertex
+        _handle(cfg, verts, coef, asm_variant=2)
 
 
 def test_separable_rejects_perturbed_mesh():

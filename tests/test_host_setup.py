@@ -51,6 +51,22 @@ def test_temporal_prolongations_match_oracle(problem, method, k, c):
         cur = co
 
 
+@pytest.mark.parametrize("problem", [0, 1])
+@pytest.mark.parametrize("method,k", [(0, 0), (0, 1), (0, 3), (1, 1), (1, 2), (1, 4)])
+def test_temporal_dof_times_match_oracle(problem, method, k):
+    c, tau, t0 = 3, 0.07, 0.4
+    got = _lib().temporal_dof_times(problem, method, k, c, tau, t0)
+    s = temporal.slab(problem, method, k, c, tau, t0)
+    assert np.allclose(got, s.times, rtol=0, atol=1e-14)
+    # closed forms: dG(0) and cGP(1) sit at the cell ends, dG(1) at the right Radau points 1/3 and 1
+    ends = t0 + tau * np.arange(1, c + 1)
+    if (method, k) in ((0, 0), (1, 1)):
+        assert np.allclose(got, ends, rtol=0, atol=1e-14)
+    if (method, k) == (0, 1):
+        assert np.allclose(got[0::2], ends - tau + tau / 3.0, rtol=0, atol=1e-14)
+        assert np.allclose(got[1::2], ends, rtol=0, atol=1e-14)
+
+
 def test_host_queries_reject_bad_arguments():
     L = _lib()
     with pytest.raises(L.StmgError):
