@@ -95,8 +95,10 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
   T* scr = xs + (size_t)n_t * NB;                     // [teams][NTC][N][N] exchange slices
   T* sQ = scr + (size_t)teams * NTC * NN;             // [3][4][N][N]
   T* sL = sQ + 3 * 4 * NN;                            // [3][4][N]
+  T* zl = sL + 3 * 4 * N;                             // one zero
   for (int e = tid; e < 3 * 4 * NN; e += nthr) sQ[e] = A.fq[e];
   for (int e = tid; e < 3 * 4 * N; e += nthr) sL[e] = A.fl[e];
+  if (tid == 0) *zl = (T)0;
   brick_stage<T, 24>(g, A.L, P, n_t, A.r, xs);
   __syncthreads();
 
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
     __syncthreads();
   }
 
-  brick_write<T, 24>(g, A.L, P, n_t, xs, A.omega, A.overwrite, (const T*)nullptr, A.u);
+  brick_write<T, 24>(g, A.L, P, n_t, xs, zl, A.omega, A.overwrite, (const T*)nullptr, A.u);
 }
 
 template <class T, int N, int NTC>
@@ -227,7 +229,7 @@ void launch_fdm_brick(const GeomDesc& g, int n_t, const double* Mtau, const doub
   A.n_t = n_t;
   BrickPlan pl;
   static const int vgprs = kernel_vgprs(k_asm_fdm_brick<T, N, NTC>);
-  if (!plan_brick(g, n_t, n_t / NTC, NTC * N, sizeof(T), NTC * N * N, sizeof(T) * 3 * 4 * (N * N + N), vgprs, pl))
+  if (!plan_brick(g, n_t, n_t / NTC, NTC * N, sizeof(T), NTC * N * N, sizeof(T) * (3 * 4 * (N * N + N) + 1), vgprs, pl))
     fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs of the smoother");
   BrickLaunch L[8];
   brick_launches(g, pl, L);

@@ -85,36 +85,55 @@ __device__ inline void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// xs[j][node] = x on the brick's nodes for every temporal plane j < n_t (Dirichlet nodes and nodes
-// past the lattice read as zero).
+// Zeros in global memory, never written: the load of a lane that needs no value reads one (lanes of
+// a wave reading one address cost one request).
+static __device__ double brick_zero_f64 = 0.0;
+static __device__ float brick_zero_f32 = 0.0f;
+__device__ inline const double* brick_zero(const double*) { return &brick_zero_f64; }
+__device__ inline const float* brick_zero(const float*) { return &brick_zero_f32; }
+
+// The batches below are straight-line code: every lane issues every load of a batch, from the node's
+// address or from a zero, so no value needs a select (or a branch) after its load returns.  With
+// conditional loads the compiler puts each load in a branch of its own and waits for it there, and
+// selects after the loads keep one lane mask per batch entry alive (more than the scalar registers
+// hold).  Global and LDS offsets advance by additions along the (lz, j) walk.
+
+// Batch size for a walk: entries past a position's last plane still cost a load, so a workgroup
+// whose positions hold few planes (small bricks) takes a smaller batch (the choice is uniform).
+__device__ inline int brick_batch(const PlaneWalk& w, const BrickLaunch& L, int n_t, int max_batch) {
+  const int per = n_t * ((L.NBd[2] + w.step - 1) / w.step);   // (lz, j) planes of one position, at most
+  return per <= 4 ? 4 : (per <= 8 || max_batch <= 8) ? 8 : max_batch;
+}
+
 template <class T, int ROW_BATCH>
-__device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
-                                   const T* __restrict__ x, T* xs) {
+__device__ inline void brick_stage_batch(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                         const T* __restrict__ x, T* xs, const PlaneWalk& w) {
   const int nbx = L.NBd[0], nbz = L.NBd[2];
   const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
   const long long nn01 = (long long)nn0 * nn1;
-  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  const T* zero = brick_zero(x);
+  const long long zstep = (long long)w.step * nn01, wrap = g.nx - (long long)nbz * nn01;
+  const int sstep = w.step * w.np, swrap = P.NB - nbz * w.np;
   for (int e = w.e0; e < w.np; e += w.estep) {
     const int ly = e / nbx, lx = e - ly * nbx;
     const int gx = P.g0[0] + lx, gy = P.g0[1] + ly;
     const bool inxy = gx > 0 && gx < nn0 - 1 && gy > 0 && gy < nn1 - 1;
-    const T* xp = x + (long long)gy * nn0 + gx;
     T* sp = xs + e;
-    int lz = w.slot, j = 0;
+    int lz = w.slot, j = 0, so = lz * w.np;
+    long long off = (long long)(P.g0[2] + lz) * nn01 + (long long)gy * nn0 + gx;
     while (j < n_t) {
       T v[ROW_BATCH];
-      int dst[ROW_BATCH];
+      int dst[ROW_BATCH];         // -1: past the last plane
 #pragma unroll
       for (int u = 0; u < ROW_BATCH; ++u) {
-        v[u] = 0;
-        dst[u] = -1;
-        if (j < n_t) {
-          const int gz = P.g0[2] + lz;
-          if (inxy && gz > 0 && gz < nn2 - 1) v[u] = xp[(long long)j * g.nx + gz * nn01];
-          dst[u] = j * P.NB + lz * w.np;
-          lz += w.step;
-          if (lz >= nbz) { lz -= nbz; ++j; }
-        }
+        const int gz = P.g0[2] + lz;
+        const bool in = j < n_t && inxy && gz > 0 && gz < nn2 - 1;
+        v[u] = *(in ? x + off : zero);
+        dst[u] = j < n_t ? so : -1;
+        lz += w.step;
+        off += zstep;
+        so += sstep;
+        if (lz >= nbz) { lz -= nbz; ++j; off += wrap; so += swrap; }
       }
 #pragma unroll
       for (int u = 0; u < ROW_BATCH; ++u)
@@ -123,21 +142,32 @@ __device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, cons
   }
 }
 
-// Write the brick's sums xs (n_t planes) to y:
-//   overwrite: y = base + scale * xs by the brick of the lowest colour holding the node (base null:
-//              zero), y += scale * xs by the others; Dirichlet nodes receive base (or zero) only;
-//   otherwise: y += scale * xs on interior nodes.
+// xs[j][node] = x on the brick's nodes for every temporal plane j < n_t (Dirichlet nodes and nodes
+// past the lattice read as zero); batches of at most ROW_BATCH loads.
 template <class T, int ROW_BATCH>
-__device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
-                                   const T* xs, T scale, int overwrite, const T* __restrict__ base, T* y) {
+__device__ inline void brick_stage(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                   const T* __restrict__ x, T* xs) {
+  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  const int rb = brick_batch(w, L, n_t, ROW_BATCH);
+  if (rb == 4) brick_stage_batch<T, 4>(g, L, P, n_t, x, xs, w);
+  else if (rb == 8) brick_stage_batch<T, 8>(g, L, P, n_t, x, xs, w);
+  else brick_stage_batch<T, ROW_BATCH>(g, L, P, n_t, x, xs, w);
+}
+
+template <class T, int ROW_BATCH>
+__device__ inline void brick_write_batch(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                         const T* xs, const T* zl, T scale, int overwrite,
+                                         const T* __restrict__ base, T* y, const PlaneWalk& w) {
   const int nbx = L.NBd[0], nbz = L.NBd[2];
   const int nn0 = g.nn[0], nn1 = g.nn[1], nn2 = g.nn[2];
   const long long nn01 = (long long)nn0 * nn1;
   const int p = g.p;
   const int last0 = P.nc[0] * p, last1 = P.nc[1] * p, last2 = P.nc[2] * p;
+  const T* zero = brick_zero(xs);
   // a node on a shared brick face is stored by the brick of the lowest colour holding it
   const bool zlo_shared = P.b[2] > 0, zhi_shared = P.b[2] + 1 < L.nbt[2], zodd = (P.b[2] & 1) != 0;
-  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  const long long zstep = (long long)w.step * nn01, wrap = g.nx - (long long)nbz * nn01;
+  const int sstep = w.step * w.np, swrap = P.NB - nbz * w.np;
   for (int e = w.e0; e < w.np; e += w.estep) {
     const int ly = e / nbx, lx = e - ly * nbx;
     if (lx > last0 || ly > last1) continue;                     // outside the brick's cells
@@ -146,40 +176,50 @@ __device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, cons
     const bool shy = (ly == 0 && P.b[1] > 0) || (ly == last1 && P.b[1] + 1 < L.nbt[1]);
     const bool fxy = !(shx && (P.b[0] & 1)) && !(shy && (P.b[1] & 1));
     const bool bxy = gx == 0 || gx == nn0 - 1 || gy == 0 || gy == nn1 - 1;
-    const long long oxy = (long long)gy * nn0 + gx;
     const T* sp = xs + e;
-    int lz = w.slot, j = 0;
+    int lz = w.slot, j = 0, so = lz * w.np;
+    long long off = (long long)(P.g0[2] + lz) * nn01 + (long long)gy * nn0 + gx;
     while (j < n_t) {
-      long long gi[ROW_BATCH];
-      int mode[ROW_BATCH];        // -1 skip, 0 boundary store, 1 store (base + v), 2 update
+      long long gi[ROW_BATCH];    // -1: no store
       T old[ROW_BATCH], v[ROW_BATCH];
 #pragma unroll
       for (int u = 0; u < ROW_BATCH; ++u) {
-        mode[u] = -1;
-        old[u] = 0;
-        v[u] = 0;
-        gi[u] = 0;
-        if (j < n_t) {
-          if (lz <= last2) {
-            const int gz = P.g0[2] + lz;
-            const bool shz = (lz == 0 && zlo_shared) || (lz == last2 && zhi_shared);
-            const bool store = overwrite && fxy && !(shz && zodd);
-            const bool bnd = bxy || gz == 0 || gz == nn2 - 1;
-            gi[u] = (long long)j * g.nx + gz * nn01 + oxy;
-            mode[u] = bnd ? (store ? 0 : -1) : (store ? 1 : 2);
-            if (mode[u] == 0 || mode[u] == 1) old[u] = base ? base[gi[u]] : (T)0;
-            else if (mode[u] == 2) old[u] = y[gi[u]];
-            if (mode[u] >= 1) v[u] = scale * sp[j * P.NB + lz * w.np];
-          }
-          lz += w.step;
-          if (lz >= nbz) { lz -= nbz; ++j; }
-        }
+        const bool ok = j < n_t && lz <= last2;
+        const int gz = P.g0[2] + lz;
+        const bool shz = (lz == 0 && zlo_shared) || (lz == last2 && zhi_shared);
+        const bool store = overwrite && fxy && !(shz && zodd);
+        const bool bnd = bxy || gz == 0 || gz == nn2 - 1;
+        const bool upd = ok && !bnd && !store;                  // y += scale v
+        const bool put = ok && store;                           // y = base + scale v (v = 0 on Dirichlet nodes)
+        old[u] = *(upd ? y + off : ((put && base) ? base + off : zero));
+        v[u] = *((ok && !bnd) ? sp + so : zl);
+        gi[u] = (upd || put) ? off : -1;
+        lz += w.step;
+        off += zstep;
+        so += sstep;
+        if (lz >= nbz) { lz -= nbz; ++j; off += wrap; so += swrap; }
       }
 #pragma unroll
       for (int u = 0; u < ROW_BATCH; ++u)
-        if (mode[u] >= 0) y[gi[u]] = old[u] + v[u];
+        if (gi[u] >= 0) y[gi[u]] = old[u] + scale * v[u];
     }
   }
+}
+
+// Write the brick's sums xs (n_t planes) to y:
+//   overwrite: y = base + scale * xs by the brick of the lowest colour holding the node (base null:
+//              zero), y += scale * xs by the others; Dirichlet nodes receive base (or zero) only;
+//   otherwise: y += scale * xs on interior nodes.
+// zl points to a zero in LDS; batches of at most ROW_BATCH loads.
+template <class T, int ROW_BATCH>
+__device__ inline void brick_write(const GeomDesc& g, const BrickLaunch& L, const BrickPos& P, int n_t,
+                                   const T* xs, const T* zl, T scale, int overwrite, const T* __restrict__ base,
+                                   T* y) {
+  const PlaneWalk w(threadIdx.x, blockDim.x, L.NBd);
+  const int rb = brick_batch(w, L, n_t, ROW_BATCH);
+  if (rb == 4) brick_write_batch<T, 4>(g, L, P, n_t, xs, zl, scale, overwrite, base, y, w);
+  else if (rb == 8) brick_write_batch<T, 8>(g, L, P, n_t, xs, zl, scale, overwrite, base, y, w);
+  else brick_write_batch<T, ROW_BATCH>(g, L, P, n_t, xs, zl, scale, overwrite, base, y, w);
 }
 
 

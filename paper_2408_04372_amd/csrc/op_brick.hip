@@ -77,8 +77,9 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
 
   T* xs = reinterpret_cast<T*>(smem_raw);                 // [n_t][NB]: input, then the brick's sums
   T* scr = xs + (size_t)n_t * NB;                          // [teams][2][N][N] exchange slices
+  T* zl = scr + (size_t)teams * 2 * N * N;                 // one zero
   const int mnnz = A.tp.mnnz, nnnz = A.tp.nnnz;
-  T* mval_s = scr + (size_t)teams * 2 * N * N;
+  T* mval_s = zl + 1;
   T* nval_s = mval_s + mnnz;
   int* mptr_s = reinterpret_cast<int*>(nval_s + nnnz);
   int* nptr_s = mptr_s + n_t + 1;
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   for (int e = tid; e < mnnz; e += nthr) { mval_s[e] = A.tp.mval[e]; mcol_s[e] = A.tp.mcol[e]; }
   for (int e = tid; e < nnnz; e += nthr) { nval_s[e] = A.tp.nval[e]; ncol_s[e] = A.tp.ncol[e]; }
   for (int e = tid; e <= n_t; e += nthr) { mptr_s[e] = A.tp.mptr[e]; nptr_s[e] = A.tp.nptr[e]; }
+  if (tid == 0) *zl = (T)0;
 
   brick_stage<T, OP_BATCH>(g, A.L, P, n_t, A.x, xs);
   __syncthreads();
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
     __syncthreads();
   }
 
-  brick_write<T, OP_BATCH>(g, A.L, P, n_t, xs, A.scale, A.overwrite, A.base, A.y);
+  brick_write<T, OP_BATCH>(g, A.L, P, n_t, xs, zl, A.scale, A.overwrite, A.base, A.y);
 }
 
 template <class T, int N>
@@ -267,7 +269,7 @@ void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T
                     T scale, hipStream_t s, const T* base, bool overwrite) {
   if (!brick_applicable(g)) fail(STMG_E_UNSUPPORTED, "the brick operator needs a 3D Cartesian level");
   if (g.ncells == 0 || tp.n_t == 0) return;
-  const size_t csr = sizeof(T) * (size_t)(tp.mnnz + tp.nnnz) +
+  const size_t csr = sizeof(T) * (size_t)(1 + tp.mnnz + tp.nnnz) +
                      sizeof(int) * (size_t)(2 * (tp.n_t + 1) + tp.mnnz + tp.nnnz);
   BrickPlan pl;
   auto run = [&](auto tag, int vgprs) {

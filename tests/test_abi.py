@@ -55,7 +55,7 @@ int main(void) {
 @pytest.mark.parametrize("field,value", [("dim", 4), ("p", 0), ("p", 7), ("k", -1), ("tau", 0.0),
                                          ("n_time_cells", 0), ("restart", 0), ("rtol", 0.0),
                                          ("precision", 5), ("n_smooth", 0), ("time_mg", 2),
-                                         ("asm_variant", 2), ("gram_schmidt", 3), ("kernel_path", 3),
+                                         ("asm_variant", 3), ("asm_variant", -1), ("gram_schmidt", 3), ("kernel_path", 3),
                                          ("kernel_path", -1)])
 def test_invalid_config_rejected_on_host(field, value):
     from paper_2408_04372_amd import _lib
