@@ -103,14 +103,16 @@ __global__ void k_dot_final(const double* __restrict__ part, int nblocks, int kc
   if (threadIdx.x == 0) out[j] = s;
 }
 
-// w -= sum_j h[j] V_j; with NORM also the partial sums of the new ||w||^2 and a non-finite flag
+// w -= sum_j h[j] hs[j] V_j (hs null: 1); with NORM also the partial sums of the new ||w||^2 and a
+// non-finite flag
 template <int KC, bool NORM>
 __global__ void k_multi_axpy_neg(const double* __restrict__ V, long long ldv, const double* __restrict__ h,
-                                 double* __restrict__ w, long long n, double* __restrict__ part) {
+                                 const double* __restrict__ hs, double* __restrict__ w, long long n,
+                                 double* __restrict__ part) {
   __shared__ double sh[BS / 64];
   double c[KC];
 #pragma unroll
-  for (int j = 0; j < KC; ++j) c[j] = h[j];
+  for (int j = 0; j < KC; ++j) c[j] = hs ? h[j] * hs[j] : h[j];
   double acc = 0.0, bad = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     double v[KC];
@@ -348,14 +350,14 @@ void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, doub
     int kc = k - j0 < JC ? k - j0 : JC;
     by_count<JC>(kc, [&](auto K) {
       hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, false>), dim3(grid_for(n)), dim3(BS), 0, s,
-                         V + j0 * ldv, ldv, h + j0, w, n, (double*)nullptr);
+                         V + j0 * ldv, ldv, h + j0, (const double*)nullptr, w, n, (double*)nullptr);
     });
     STMG_CHECK_LAUNCH();
   }
 }
 
 void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h, double* w, long long n,
-                         double* out, double* part, hipStream_t s) {
+                         double* out, double* part, hipStream_t s, const double* hs) {
   unsigned nb = grid_for(n);
   if (nb > RED_BLOCKS) nb = RED_BLOCKS;
   for (int j0 = 0; j0 < k; j0 += JC) {
@@ -364,10 +366,10 @@ void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h,
     by_count<JC>(kc, [&](auto K) {
       if (last)
         hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, true>), dim3(nb), dim3(BS), 0, s,
-                           V + j0 * ldv, ldv, h + j0, w, n, part);
+                           V + j0 * ldv, ldv, h + j0, hs ? hs + j0 : hs, w, n, part);
       else
         hipLaunchKernelGGL((k_multi_axpy_neg<decltype(K)::value, false>), dim3(grid_for(n)), dim3(BS), 0, s,
-                           V + j0 * ldv, ldv, h + j0, w, n, (double*)nullptr);
+                           V + j0 * ldv, ldv, h + j0, hs ? hs + j0 : hs, w, n, (double*)nullptr);
     });
     STMG_CHECK_LAUNCH();
   }

@@ -250,24 +250,30 @@ inline int kernel_vgprs(K kernel) {
 //     (its staging, compute and write-back phases then run back to back),
 // with at most 8 waves, every work item of the brick (items_per_cell per cell, one team of
 // team_lanes lanes each, teams never straddling a wave) in one round of teams, and LDS (n_t planes
-// of the box, team_scratch values per team, plus `extra` bytes) within 72 KB.
+// of the box, team_scratch values per team, plus `extra` bytes; with scratch_in_box the team scratch
+// reuses the box's planes and the larger of the two counts) within 72 KB.
 inline bool plan_brick(const GeomDesc& g, int n_t, int items_per_cell, int team_lanes, size_t elem,
-                       int team_scratch, size_t extra, int vgprs, BrickPlan& out) {
+                       int team_scratch, size_t extra, int vgprs, BrickPlan& out, bool scratch_in_box = false,
+                       bool long_bricks = false) {
   const int p = g.p;
   const int tpw = 64 / team_lanes;
   const int vg = std::max(8, (vgprs + 7) / 8 * 8);
   const int waves_simd = std::max(1, std::min(8, 512 / vg));
   static const int cand[][3] = {{4, 3, 2}, {4, 2, 2}, {3, 3, 2}, {3, 2, 2}, {2, 3, 2}, {2, 2, 2}, {6, 2, 1},
-                                {4, 3, 1}, {4, 2, 1}, {3, 3, 1}, {3, 2, 1}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+                                {4, 3, 1}, {4, 2, 1}, {3, 3, 1}, {3, 2, 1}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1},
+                                {6, 3, 2}, {8, 2, 2}, {16, 1, 1}};
+  const int ncand = long_bricks ? 17 : 14;
   double best = -1.0;
-  for (auto& c : cand) {
+  for (int ci = 0; ci < ncand; ++ci) {
+    const int* c = cand[ci];
     int B[3] = {std::min(c[0], g.nc[0]), std::min(c[1], g.nc[1]), std::min(c[2], g.nc[2])};
     const long long items = (long long)B[0] * B[1] * B[2] * items_per_cell;
     const int waves = (int)((items + tpw - 1) / tpw);
     if (waves > 8) continue;
     const int nbd0 = p * B[0] + 1;
     const long long nb = (long long)nbd0 * (p * B[1] + 1) * (p * B[2] + 1);
-    const size_t lds = elem * ((size_t)n_t * nb + (size_t)waves * tpw * team_scratch) + extra;
+    const size_t box = (size_t)n_t * nb, scr = (size_t)waves * tpw * team_scratch;
+    const size_t lds = elem * (scratch_in_box ? std::max(box, scr) : box + scr) + extra;
     if (lds > 72 * 1024) continue;
     const double owned = (double)(p * B[0]) * (p * B[1]) * (p * B[2]) / (double)nb;
     const double row = (double)(nbd0 * elem) / (double)(nbd0 * elem + 64);

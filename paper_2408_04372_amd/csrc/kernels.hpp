@@ -76,9 +76,10 @@ void multi_dot(const double* V, long long ldv, int k, const double* w, long long
 // w -= sum_j h[j] V_j  (h on device)
 void multi_axpy_neg(const double* V, long long ldv, int k, const double* h, double* w, long long n,
                     hipStream_t s);
-// w -= sum_j h[j] V_j, then out[0] = w . w and out[1] = 1 if w holds NaN/Inf (else 0)
+// w -= sum_j h[j] hs[j] V_j (hs on device, null: 1), then out[0] = w . w and out[1] = 1 if w holds
+// NaN/Inf (else 0)
 void multi_axpy_neg_norm(const double* V, long long ldv, int k, const double* h, double* w, long long n,
-                         double* out, double* ws, hipStream_t s);
+                         double* out, double* ws, hipStream_t s, const double* hs = nullptr);
 // x += sum_j y[j] Z_j  (y on device, Z in T)
 template <class T>
 void multi_axpy_acc(const T* Z, long long ldz, int k, const double* y, double* x, long long n,

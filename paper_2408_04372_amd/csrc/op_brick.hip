@@ -75,9 +75,10 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
   const int c0x = P.c0[0], c0y = P.c0[1], c0z = P.c0[2];
 
-  T* xs = reinterpret_cast<T*>(smem_raw);                 // [n_t][NB]: input, then the brick's sums
-  T* scr = xs + (size_t)n_t * NB;                          // [teams][2][N][N] exchange slices
-  T* zl = scr + (size_t)teams * 2 * N * N;                 // one zero
+  // [n_t][NB]: input, then the exchange slices of phase 2 ([teams][2][N][N]), then the brick's sums
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  T* scr = xs;
+  T* zl = xs + (size_t)max(n_t * NB, teams * 2 * N * N);   // one zero
   const int mnnz = A.tp.mnnz, nnnz = A.tp.nnnz;
   T* mval_s = zl + 1;
   T* nval_s = mval_s + mnnz;
@@ -142,8 +143,6 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
     }
   }
   __syncthreads();                                         // every team has read its input
-  for (int e = tid; e < n_t * NB; e += nthr) xs[e] = (T)0;
-  __syncthreads();
 
   // phase 2, one x slice at a time: z sweeps (lane t = y), exchange, y sweeps (lane t = z)
   T Y[N][N];                                               // [y][x] of plane z = t
@@ -183,6 +182,10 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
     }
     wave_sync_lds();
   }
+
+  __syncthreads();                                         // every team is done with its slices
+  for (int e = tid; e < n_t * NB; e += nthr) xs[e] = (T)0;
+  __syncthreads();
 
   // sum the cell results into the brick, one cell parity class per round
   const int par = (lcx & 1) | ((lcy & 1) << 1) | ((lcz & 1) << 2);
@@ -274,7 +277,7 @@ void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T
   BrickPlan pl;
   auto run = [&](auto tag, int vgprs) {
     constexpr int N = decltype(tag)::value;
-    if (!plan_brick(g, tp.n_t, tp.n_t, N, sizeof(T), 2 * N * N, csr, vgprs, pl))
+    if (!plan_brick(g, tp.n_t, tp.n_t, N, sizeof(T), 2 * N * N, csr, vgprs, pl, true, true))
       fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs");
     launch_brick<T, N>(g, ct, tp, x, y, scale, base, overwrite, pl, s);
   };

@@ -24,7 +24,7 @@ void ensure_workspace(stmg_handle* h, long long n, int m) {
   h->V.alloc(sizeof(double) * n * (m + 1));
   h->w.alloc(sizeof(double) * n);
   h->red.alloc(sizeof(double) * RED_BLOCKS * PS);
-  h->dots.alloc(sizeof(double) * (m + 4));
+  h->dots.alloc(sizeof(double) * (2 * m + 6));   // dot products and norms, then squared basis scales
   if (need32) {
     h->Z32.alloc(sizeof(float) * n * m);
     h->tmp32a.alloc(sizeof(float) * n);
@@ -63,6 +63,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
   double* b = h->w.as<double>();
   double* dots = h->dots.as<double>();
   double* red = h->red.as<double>();
+  double* s2d = dots + m + 4;
   stmg_solve_info inf{};
   h->timer.on = true;
   h->timer.reset();
@@ -91,6 +92,17 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
     fill<double>(x, 0.0, n, s);
   } else {
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    // Basis vectors are stored unnormalised, v_i = sc[i] V_i, and the scales enter the Gram-Schmidt
+    // coefficients (device copy s2d = sc^2), the Hessenberg entries and the update of x, which saves
+    // a scaling pass over every new vector.  A V-cycle is linear, so Z_i = V(V_i) = V(v_i) / sc[i].
+    // The learned stage is not linear and sees unit vectors (sc = 1, explicit scaling).
+    const bool lazy = !learned;
+    std::vector<double> sc(m + 1, 1.0), s2h(m + 1, 1.0);
+    auto set_scale = [&](int i, double v) {
+      sc[i] = v;
+      s2h[i] = v * v;
+      STMG_HIP(hipMemcpyAsync(s2d + i, &s2h[i], sizeof(double), hipMemcpyHostToDevice, s));
+    };
     for (;;) {
       // true residual r = b - S x into V_0
       h->timer.mark(TB_OP, s);
@@ -105,7 +117,8 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
       if (rel <= h->cfg.rtol) break;
       if (it >= h->cfg.max_iter) { status = STMG_E_NOCONV; break; }
       if (it > 0) inf.restarts++;
-      scal<double>(1.0 / beta, V, n, s);
+      if (lazy) set_scale(0, 1.0 / beta);
+      else scal<double>(1.0 / beta, V, n, s);
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int jused = 0;
@@ -173,19 +186,22 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
           // dots[0..j] = V^T w, dots[j+1] = ||w||^2, then dots[j+2..j+3] = ||w'||^2 and the
           // non-finite flag of the update: one read-back per pass
           multi_dot(V, n, j + 1, vn, n, dots, red, s, true);
-          multi_axpy_neg_norm(V, n, j + 1, dots, vn, n, dots + j + 2, red, s);
+          multi_axpy_neg_norm(V, n, j + 1, dots, vn, n, dots + j + 2, red, s, lazy ? s2d : nullptr);
           std::vector<double> hv = download<double>(dots, j + 4, s);
           w2.assign(hv.begin() + j + 2, hv.begin() + j + 4);
-          for (int i = 0; i <= j; ++i) hc[i] += hv[i];
+          for (int i = 0; i <= j; ++i) hc[i] += hv[i] * sc[i] * sc[j];
           const double ww = hv[j + 1];
           if (!std::isfinite(ww) || w2[1] != 0.0) { bad = true; break; }
           if (h->cfg.gram_schmidt == 0 && w2[0] >= GS_REFINE * GS_REFINE * ww) break;
         }
         if (bad) break;
-        double hn = std::sqrt(w2[0]);
+        const double hraw = std::sqrt(w2[0]), hn = sc[j] * hraw;
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
         H[(size_t)(j + 1) * m + j] = hn;
-        if (hn > 0.0) scal<double>(1.0 / hn, vn, n, s);
+        if (hraw > 0.0) {
+          if (lazy) set_scale(j + 1, 1.0 / hraw);
+          else scal<double>(1.0 / hraw, vn, n, s);
+        }
         for (int i = 0; i < j; ++i) {
           double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
           H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
@@ -210,6 +226,7 @@ stmg_status fgmres(stmg_handle* h, const double* b_in, double* x, stmg_solve_inf
         for (int k = i + 1; k < jused; ++k) sum -= H[(size_t)i * m + k] * y[k];
         y[i] = sum / H[(size_t)i * m + i];
       }
+      for (int i = 0; i < jused; ++i) y[i] *= sc[i];
       STMG_HIP(hipMemcpyAsync(dots, y.data(), sizeof(double) * jused, hipMemcpyHostToDevice, s));
       if (mixed) multi_axpy_acc<float>(h->Z32.as<float>(), n, jused, dots, x, n, s);
       else multi_axpy_acc<double>(h->Z64.as<double>(), n, jused, dots, x, n, s);

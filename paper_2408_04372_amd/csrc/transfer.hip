@@ -183,13 +183,18 @@ __global__ __launch_bounds__(256) void k_tensor3(const T* __restrict__ in, T* __
     }
   }
   if (own) {
+    const int kl = out2 - 1 - oz0;                           // last plane of the chunk inside the lattice
+    if (accumulate) {
+      // every old value is loaded before the first store (planes past the lattice reload the last one)
+      T old[TZC];
+#pragma unroll
+      for (int k = 0; k < TZC; ++k) old[k] = dst[(k < kl ? k : kl) * zstride];
+#pragma unroll
+      for (int k = 0; k < TZC; ++k) acc[k] += old[k];
+    }
 #pragma unroll
     for (int k = 0; k < TZC; ++k)
-      if (oz0 + k < out2) {
-        T* o = dst + k * zstride;
-        if (accumulate) *o += acc[k];
-        else *o = acc[k];
-      }
+      if (k <= kl) dst[k * zstride] = acc[k];
   }
 }
 
