@@ -6,10 +6,10 @@
 // eigenvalues; one ntc x ntc temporal solve per spatial mode and time cell.
 //
 // MI355X mapping (brick tiling in brick.hpp).  A team of ntc (p+1) lanes owns one (cell, time
-// cell); lane (d, t) holds temporal DoF d and first the y = t plane ([z][x]: the forward x and z
-// transforms are lane local); a per-x-slice exchange through a small LDS scratch hands it the z = t
-// plane ([y][x]), where it applies Q_y^T, the temporal solves of its modes (the other temporal DoFs
-// of a mode come from the team's other lanes by a cross-lane shuffle) and Q_y in the same slice,
+// cell); lane (d, t) (team lane NTC t + d) holds temporal DoF d and first the y = t plane ([z][x]:
+// the forward x and z transforms are lane local); a per-x-slice exchange through a small LDS scratch
+// hands it the z = t plane ([y][x]), where it applies Q_y^T, the temporal solves of its modes (the
+// other temporal DoF of a mode comes from the neighbouring lane by a DPP permutation) and Q_y,
 // then Q_x; a second per-slice exchange returns the y = t plane, where Q_z completes the correction.  The 1D tables sit in LDS; the corrections are summed into
 // the brick's LDS copy by cell parity class and written once per node.
 #include "brick.hpp"
@@ -34,21 +34,25 @@ struct BrickFdmArgs {
   BrickLaunch L;
 };
 
-// solve (lam M + N~) w = b for one spatial mode: one or two temporal DoFs per time cell, in closed
-// form (Cramer's rule for 2 x 2)
-template <class T, int NTC>
-__device__ inline void mode_solve(const T (&Mt)[NTC][NTC], const T (&Nt)[NTC][NTC], T lam, T (&b)[NTC]) {
-  if constexpr (NTC == 1) {
-    b[0] = b[0] / (lam * Mt[0][0] + Nt[0][0]);
-  } else {
-    const T a00 = lam * Mt[0][0] + Nt[0][0], a01 = lam * Mt[0][1] + Nt[0][1];
-    const T a10 = lam * Mt[1][0] + Nt[1][0], a11 = lam * Mt[1][1] + Nt[1][1];
-    const T inv = (T)1 / (a00 * a11 - a01 * a10);
-    const T w0 = (a11 * b[0] - a01 * b[1]) * inv;
-    const T w1 = (a00 * b[1] - a10 * b[0]) * inv;
-    b[0] = w0;
-    b[1] = w1;
-  }
+// 1 / a: the hardware estimate refined by two Newton-Raphson steps r <- r + r (1 - a r) (FP64), or
+// the division (FP32)
+__device__ inline double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(fma(-a, r, 1.0), r, r);
+  r = fma(fma(-a, r, 1.0), r, r);
+  return r;
+}
+__device__ inline float recip(float a) { return 1.0f / a; }
+
+// the value of lane l ^ 1 (DPP quad permutation [1, 0, 3, 2]; every lane of the wave is active)
+__device__ inline float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline double pair_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // In-place 1D transform of the lane's 5 x 5 plane A[r][c] along the column index (ALONG_COL) or the
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
 
   const int wave = tid >> 6, lane = tid & 63;
   const int tw = lane / TL, tl = lane - tw * TL;
-  const int d = tl / N, t = tl - d * N;               // this lane's temporal DoF and plane
+  const int d = tl % NTC, t = tl / NTC;               // this lane's temporal DoF and plane
   const int team = wave * TPW + tw;
   const int ncell = P.nc[0] * P.nc[1] * P.nc[2];
   const bool act = tw < TPW && team < ncell * c;
@@ -153,10 +157,10 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
     wave_sync_lds();
   }
   sweep_inplace<T, N, false, true>(Q[1], S);         // S[y][x]: along y
-  // temporal solve of every mode (x, y, z = t); the other temporal DoFs of a mode come from the
-  // team's lanes of the same plane
+  // temporal solve (lam M_tau + N~) w = b of every mode (x, y, z = t), lam = rho (lx + ly + lz), in
+  // closed form (Cramer's rule for two temporal DoFs); with two, the mode's other DoF sits in the
+  // neighbouring lane (lane = team base + NTC t + d) and each lane forms its own component
   {
-    const int lane0 = tw * TL + t;
     const T lz_t = lam[2][t];
     T lx[N], ly[N];
 #pragma unroll
@@ -165,14 +169,16 @@ __global__ __launch_bounds__(512) void k_asm_fdm_brick(BrickFdmArgs<T, NTC> A) {
     for (int y = 0; y < N; ++y)
 #pragma unroll
       for (int x = 0; x < N; ++x) {
-        T b[NTC];
-#pragma unroll
-        for (int e = 0; e < NTC; ++e) b[e] = NTC == 1 ? S[y][x] : __shfl(S[y][x], lane0 + e * N);
-        mode_solve<T, NTC>(A.Mt, A.Nt, rho * (lx[x] + ly[y] + lz_t), b);
-        T mine = b[0];
-#pragma unroll
-        for (int e = 1; e < NTC; ++e) mine = d == e ? b[e] : mine;
-        S[y][x] = mine;
+        const T lm = rho * (lx[x] + ly[y] + lz_t);
+        if constexpr (NTC == 1) {
+          S[y][x] = S[y][x] * recip(lm * A.Mt[0][0] + A.Nt[0][0]);
+        } else {
+          const T own = S[y][x], oth = pair_swap(own);
+          const T a00 = lm * A.Mt[0][0] + A.Nt[0][0], a01 = lm * A.Mt[0][1] + A.Nt[0][1];
+          const T a10 = lm * A.Mt[1][0] + A.Nt[1][0], a11 = lm * A.Mt[1][1] + A.Nt[1][1];
+          const T inv = recip(a00 * a11 - a01 * a10);
+          S[y][x] = (d == 0 ? a11 * own - a01 * oth : a00 * own - a10 * oth) * inv;
+        }
       }
   }
   sweep_inplace<T, N, false, false>(Q[1], S);        // back along y

@@ -30,6 +30,9 @@ struct TemporalDev {
   int mnnz = 0, nnnz = 0;   // stored entries of M_T and N_T
   const int* mptr = nullptr; const int* mcol = nullptr; const T* mval = nullptr;
   const int* nptr = nullptr; const int* ncol = nullptr; const T* nval = nullptr;
+  // union pattern of M_T and N_T with both values per entry (zero where one of them has none)
+  int unnz = 0;
+  const int* uptr = nullptr; const int* ucol = nullptr; const T* umval = nullptr; const T* unval = nullptr;
 };
 
 // 1D tables of Q_p with GLL nodes at the (p+1)-point Gauss rule:

@@ -40,6 +40,7 @@ struct LevelData {            // precision-dependent data of one level
 template <class T>
 struct TemporalBufs {
   DevBuf mptr, mcol, mval, nptr, ncol, nval;
+  DevBuf uptr, ucol, umval, unval;
   TemporalDev<T> dev;
 };
 

@@ -137,6 +137,25 @@ void make_temporal(const hm::Temporal& tm, TemporalBufs<T>& tb, hipStream_t s) {
   tb.dev.n_t = tm.n_t;
   tb.dev.mptr = tb.mptr.template as<int>(); tb.dev.mcol = tb.mcol.template as<int>(); tb.dev.mval = tb.mval.template as<T>();
   tb.dev.nptr = tb.nptr.template as<int>(); tb.dev.ncol = tb.ncol.template as<int>(); tb.dev.nval = tb.nval.template as<T>();
+  std::vector<int> up{0}, uc;
+  std::vector<T> um, un;
+  for (int i = 0; i < tm.n_t; ++i) {
+    for (int j = 0; j < tm.n_t; ++j)
+      if (tm.M_T(i, j) != 0.0 || tm.N_T(i, j) != 0.0) {
+        uc.push_back(j);
+        um.push_back((T)tm.M_T(i, j));
+        un.push_back((T)tm.N_T(i, j));
+      }
+    up.push_back((int)uc.size());
+  }
+  tb.dev.unnz = (int)uc.size();
+  if (uc.empty()) { uc.push_back(0); um.push_back(0); un.push_back(0); }
+  tb.uptr = upload(up, s);
+  tb.ucol = upload(uc, s);
+  tb.umval = upload(um, s);
+  tb.unval = upload(un, s);
+  tb.dev.uptr = tb.uptr.template as<int>(); tb.dev.ucol = tb.ucol.template as<int>();
+  tb.dev.umval = tb.umval.template as<T>(); tb.dev.unval = tb.unval.template as<T>();
 }
 
 }  // namespace

@@ -79,16 +79,14 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   T* xs = reinterpret_cast<T*>(smem_raw);
   T* scr = xs;
   T* zl = xs + (size_t)max(n_t * NB, teams * 2 * N * N);   // one zero
-  const int mnnz = A.tp.mnnz, nnnz = A.tp.nnnz;
-  T* mval_s = zl + 1;
-  T* nval_s = mval_s + mnnz;
-  int* mptr_s = reinterpret_cast<int*>(nval_s + nnnz);
-  int* nptr_s = mptr_s + n_t + 1;
-  int* mcol_s = nptr_s + n_t + 1;
-  int* ncol_s = mcol_s + mnnz;
-  for (int e = tid; e < mnnz; e += nthr) { mval_s[e] = A.tp.mval[e]; mcol_s[e] = A.tp.mcol[e]; }
-  for (int e = tid; e < nnnz; e += nthr) { nval_s[e] = A.tp.nval[e]; ncol_s[e] = A.tp.ncol[e]; }
-  for (int e = tid; e <= n_t; e += nthr) { mptr_s[e] = A.tp.mptr[e]; nptr_s[e] = A.tp.nptr[e]; }
+  // rows of M_T and N_T on their union pattern: x_j is read once for both products
+  const int unnz = A.tp.unnz;
+  T* um_s = zl + 1;
+  T* un_s = um_s + unnz;
+  int* uptr_s = reinterpret_cast<int*>(un_s + unnz);
+  int* ucol_s = uptr_s + n_t + 1;
+  for (int e = tid; e < unnz; e += nthr) { um_s[e] = A.tp.umval[e]; un_s[e] = A.tp.unval[e]; ucol_s[e] = A.tp.ucol[e]; }
+  for (int e = tid; e <= n_t; e += nthr) uptr_s[e] = A.tp.uptr[e];
   if (tid == 0) *zl = (T)0;
 
   brick_stage<T, OP_BATCH>(g, A.L, P, n_t, A.x, xs);
@@ -109,24 +107,21 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   T U[N][N], V[N][N];                                      // [z][x]
   {
     const T* xc = xs + ((size_t)(lcz * p) * nby + (lcy * p + t)) * nbx + lcx * p;
-    const int mk0 = act ? mptr_s[i] : 0, mk1 = act ? mptr_s[i + 1] : 0;
-    const int nk0 = act ? nptr_s[i] : 0, nk1 = act ? nptr_s[i + 1] : 0;
+    const int k0 = act ? uptr_s[i] : 0, k1 = act ? uptr_s[i + 1] : 0;
 #pragma unroll
     for (int z = 0; z < N; ++z) {
       T a[N], b[N];
 #pragma unroll
       for (int x = 0; x < N; ++x) { a[x] = 0; b[x] = 0; }
-      for (int k = mk0; k < mk1; ++k) {
-        const T c = mval_s[k];
-        const T* r = xc + (size_t)mcol_s[k] * NB + z * nby * nbx;
+      for (int k = k0; k < k1; ++k) {
+        const T cmk = um_s[k], cnk = un_s[k];
+        const T* r = xc + (size_t)ucol_s[k] * NB + z * nby * nbx;
 #pragma unroll
-        for (int x = 0; x < N; ++x) a[x] += c * r[x];
-      }
-      for (int k = nk0; k < nk1; ++k) {
-        const T c = nval_s[k];
-        const T* r = xc + (size_t)ncol_s[k] * NB + z * nby * nbx;
-#pragma unroll
-        for (int x = 0; x < N; ++x) b[x] += c * r[x];
+        for (int x = 0; x < N; ++x) {
+          const T v = r[x];
+          a[x] += cmk * v;
+          b[x] += cnk * v;
+        }
       }
 #pragma unroll
       for (int x = 0; x < N; ++x) {
@@ -187,7 +182,8 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   for (int e = tid; e < n_t * NB; e += nthr) xs[e] = (T)0;
   __syncthreads();
 
-  // sum the cell results into the brick, one cell parity class per round
+  // sum the cell results into the brick, one cell parity class per round (cells of a class share
+  // no node, so each sum is one LDS add without conflicts and the order is fixed)
   const int par = (lcx & 1) | ((lcy & 1) << 1) | ((lcz & 1) << 2);
   T* o = xs + (size_t)i * NB + ((size_t)(lcz * p + t) * nby + lcy * p) * nbx + lcx * p;
   for (int r = 0; r < 8; ++r) {
@@ -195,7 +191,8 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
 #pragma unroll
       for (int yy = 0; yy < N; ++yy)
 #pragma unroll
-        for (int xx = 0; xx < N; ++xx) o[yy * nbx + xx] += Y[yy][xx];
+        for (int xx = 0; xx < N; ++xx)
+          __hip_atomic_fetch_add(o + yy * nbx + xx, Y[yy][xx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
   }
@@ -272,8 +269,8 @@ void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T
                     T scale, hipStream_t s, const T* base, bool overwrite) {
   if (!brick_applicable(g)) fail(STMG_E_UNSUPPORTED, "the brick operator needs a 3D Cartesian level");
   if (g.ncells == 0 || tp.n_t == 0) return;
-  const size_t csr = sizeof(T) * (size_t)(1 + tp.mnnz + tp.nnnz) +
-                     sizeof(int) * (size_t)(2 * (tp.n_t + 1) + tp.mnnz + tp.nnnz);
+  if (!tp.uptr) fail(STMG_E_STATE, "temporal factors without their union pattern");
+  const size_t csr = sizeof(T) * (size_t)(1 + 2 * tp.unnz) + sizeof(int) * (size_t)(tp.n_t + 1 + tp.unnz);
   BrickPlan pl;
   auto run = [&](auto tag, int vgprs) {
     constexpr int N = decltype(tag)::value;
