@@ -260,8 +260,10 @@ void fdm_brick_ntc(const GeomDesc& g, int n_t, int ntc, const double* Mtau, cons
 
 }  // namespace
 
+// the smoother takes one coefficient per cell (frho), so levels with quadrature-point coefficients
+// qualify as well
 bool fdm_brick_applicable(const GeomDesc& g, int nt_cell) {
-  return brick_applicable(g) && nt_cell >= 1 && nt_cell <= 2;
+  return g.dim == 3 && !g.verts && g.n >= 2 && g.n <= MAXN && nt_cell >= 1 && nt_cell <= 2;
 }
 
 template <class T>

@@ -985,7 +985,8 @@ template <class T> static void asm_step(stmg_handle* h, Level& L, const T* r, T*
   LevelData<T>& d = ldata<T>(L);
   T* cb = h->cfg.asm_variant == 2 ? nullptr : d.cellbuf.template as<T>();   // patches add into u
   const bool u_zero_in = u_zero;       // the brick smoother writes u itself
-  const bool brick_fdm = h->cfg.asm_variant == 1 && L.brick && fdm_brick_applicable(L.g, L.ts->tm.nt_cell);
+  const bool brick_fdm = h->cfg.asm_variant == 1 && h->cfg.kernel_path == STMG_PATH_DEFAULT &&
+                         fdm_brick_applicable(L.g, L.ts->tm.nt_cell);
   if (u_zero && !cb && !brick_fdm) fill<T>(u, (T)0, L.nst(L.n_t()), h->stream);
   u_zero = u_zero && cb;
   h->timer.mark(TB_SMOOTH, h->stream);
