@@ -183,7 +183,7 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
   __syncthreads();
 
   // sum the cell results into the brick, one cell parity class per round (cells of a class share
-  // no node, so each sum is one LDS add without conflicts and the order is fixed)
+  // no node, so each sum meets no other one and the order is fixed)
   const int par = (lcx & 1) | ((lcy & 1) << 1) | ((lcz & 1) << 2);
   T* o = xs + (size_t)i * NB + ((size_t)(lcz * p + t) * nby + lcy * p) * nbx + lcx * p;
   for (int r = 0; r < 8; ++r) {
@@ -191,8 +191,12 @@ __global__ __launch_bounds__(512) void st_apply3_brick(BrickOpArgs<T, N> A) {
 #pragma unroll
       for (int yy = 0; yy < N; ++yy)
 #pragma unroll
-        for (int xx = 0; xx < N; ++xx)
-          __hip_atomic_fetch_add(o + yy * nbx + xx, Y[yy][xx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int xx = 0; xx < N; ++xx) {
+          if constexpr (sizeof(T) == 8)    // one LDS add instruction (measured slower for FP32)
+            __hip_atomic_fetch_add(o + yy * nbx + xx, Y[yy][xx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          else
+            o[yy * nbx + xx] += Y[yy][xx];
+        }
     }
     __syncthreads();
   }
@@ -274,7 +278,8 @@ void st_apply_brick(const GeomDesc& g, const CartTables& ct, const TemporalDev<T
   BrickPlan pl;
   auto run = [&](auto tag, int vgprs) {
     constexpr int N = decltype(tag)::value;
-    if (!plan_brick(g, tp.n_t, tp.n_t, N, sizeof(T), 2 * N * N, csr, vgprs, pl, true, true))
+    // long bricks measured faster in FP64 (lower degrees) and slower in FP32 (Q4: 16 x 1 x 1)
+    if (!plan_brick(g, tp.n_t, tp.n_t, N, sizeof(T), 2 * N * N, csr, vgprs, pl, true, sizeof(T) == 8))
       fail(STMG_E_UNSUPPORTED, "no brick fits the temporal DoFs");
     launch_brick<T, N>(g, ct, tp, x, y, scale, base, overwrite, pl, s);
   };
