@@ -2,6 +2,7 @@
 // bases, temporal matrices of dG(k)/cGP(k) and small dense linear algebra.
 #pragma once
 
+#include <cstddef>
 #include <vector>
 
 namespace stmg {
