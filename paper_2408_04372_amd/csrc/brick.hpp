@@ -6,7 +6,8 @@
 // every node of the brick is then written to HBM once.  Bricks are launched in 2^3 parity colours:
 // bricks of one colour share no node, and a node on a brick face is stored by the brick of the
 // lowest colour holding it (with the base vector, in overwrite mode) and updated by the others in
-// colour order.  The summation order is fixed, so results are bitwise reproducible, without atomics.
+// colour order.  The summation order is fixed (no two additions of a round meet at a node; in FP64
+// they are single LDS add instructions), so results are bitwise reproducible, with no global atomics.
 #pragma once
 
 #include <algorithm>
